@@ -1,0 +1,22 @@
+"""Plain FP64 CPU oracle for RGF / n-diagonal RGF / DDRGF selected inversion.
+
+TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+benchmark's CPU-baseline leg may import this package.  The GPU library never
+calls it and shares no code with it; a product path that routes through here
+would be a CPU fallback and is forbidden.
+"""
+from .rgf_oracle import (  # noqa: F401
+    OpCounter,
+    block_accessor,
+    dense_matrix,
+    dense_selected,
+    ddrgf,
+    domain_layout,
+    grad_onsite,
+    gamma_of,
+    nrgf,
+    rgf,
+    solve_energy,
+    transmission,
+    transmission_g11,
+)
