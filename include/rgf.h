@@ -1,0 +1,119 @@
+/*
+ * rgf.h — C ABI of the MI355X (gfx950) recursive Green's function library.
+ *
+ * The library computes the selected inverse bndiag(M^{-1}) of the block n-diagonal
+ * matrix M(E) = (E + i*eta_d) I - H - Sigma_L(E) (+) Sigma_R(E) for many energies E
+ * (paper "Revisiting recursive methods for Dyson and Keldysh in NEGF: Part I",
+ * Sec. 2 introduction: the Dyson problem is to extract the block n-diagonal part
+ * of the inverse of the block n-diagonal matrix M), and the transmission
+ *     T(E) = Re Tr[Gamma_L G_{0,l-1} Gamma_R G_{0,l-1}^H],  Gamma = i (Sigma - Sigma^H).
+ * Two methods: the sequential Schur-complement sweep (Sec. 2.2 Algorithm 1 for
+ * w = 1, Sec. 2.3 for w > 1) and domain-decomposition RGF (Sec. 3, Algorithm 2).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Complex numbers are interleaved pairs of double (the torch.complex128 layout).
+ *    Every b x b block is row-major and contiguous.
+ *  - Layers are numbered 0..l-1.  A block band of half-bandwidth w is stored as
+ *    X[2w+1][l][b][b] where X[w+k][i] is the block (i, i+k), k in [-w, w]; blocks
+ *    with i+k outside [0, l) are never read and never written.
+ *  - H: the band of the device Hamiltonian, shared by all energies (device memory).
+ *    H is not assumed Hermitian.  sigma_L / sigma_R: [nE][b][b] retarded lead
+ *    self-energies (device memory), attached to layer 0 and layer l-1; they
+ *    already include the lead's own broadening.  energies: [nE] doubles (device).
+ *  - G: output band [nE][2w+1][l][b][b] (device).  T: [nE] doubles (device),
+ *    may be NULL.  info: [nE] int32 (device): 0 = ok; j+1 = layer j held the first
+ *    Schur pivot (in elimination order) that was exactly singular or non-finite;
+ *    every output of that energy is then set to NaN.
+ *  - Ownership: the caller allocates and owns every input, output and workspace;
+ *    a plan owns only host metadata.  Solve calls allocate nothing, never
+ *    synchronise the stream and return as soon as the work is queued.
+ *  - stream is a hipStream_t (NULL = the default stream).
+ *  - Errors: argument and plan errors are returned synchronously; numerical
+ *    failures are reported per energy through info[] (read after a stream sync).
+ *    No entry point aborts or throws.
+ *  - A plan is immutable after creation and may be used concurrently on different
+ *    streams with distinct workspaces.
+ */
+#ifndef RGF_MI355X_H
+#define RGF_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rgf_plan_s* rgf_plan_t;
+
+typedef enum {
+  RGF_OK = 0,
+  RGF_ERR_INVALID_ARG = 1,
+  RGF_ERR_UNSUPPORTED = 2,
+  RGF_ERR_OUT_OF_MEMORY = 3,
+  RGF_ERR_WORKSPACE_TOO_SMALL = 4,
+  RGF_ERR_HIP = 5,
+  RGF_ERR_PLAN_MISMATCH = 6
+} rgf_status_t;
+
+typedef enum {
+  RGF_FP64 = 0,          /* every product and pivot in FP64 */
+  RGF_MIXED_FP32 = 1,    /* reserved: FP32 products, FP64 pivots */
+  RGF_MIXED_BF16X3 = 2   /* reserved: split-BF16 products, FP64 pivots */
+} rgf_precision_t;
+
+typedef enum {
+  RGF_METHOD_SEQUENTIAL = 0,  /* Schur-complement sweep, Algorithm 1 / Sec. 2.3 */
+  RGF_METHOD_DDRGF = 1        /* domain decomposition, Algorithm 2 */
+} rgf_method_t;
+
+/* Problem description (host memory). */
+typedef struct {
+  int64_t num_layers;        /* l >= 1 */
+  int64_t block_size;        /* b, 1 <= b <= 128 */
+  int64_t half_bandwidth;    /* w >= 1 (1 = block tridiagonal); w < l */
+  int64_t num_energies;      /* nE >= 1 */
+  int32_t precision;         /* rgf_precision_t */
+  int32_t method;            /* rgf_method_t */
+  int64_t num_domains;       /* DDRGF: number of (interior, separator) pairs m >= 1 */
+  int64_t separator_layers;  /* DDRGF: layers per separator; 0 means w (the only value supported) */
+  int32_t want_transmission; /* nonzero: T is computed when the T pointer is not NULL */
+  int32_t reserved0;
+  int64_t reserved1;
+} rgf_desc_t;
+
+/* Validate a description and build a plan.  *workspace_bytes receives the size of
+ * the device workspace that rgf_solve / ddrgf_solve need.  Validation: l >= 1,
+ * 1 <= b <= 128, 1 <= w, w < l unless l == 1, nE >= 1; DDRGF additionally needs
+ * m >= 1 and every interior at least w layers long with separators of w layers
+ * (l - m*w >= m*w).  Returns synchronously. */
+rgf_status_t rgf_plan_create(const rgf_desc_t* desc, rgf_plan_t* plan, size_t* workspace_bytes);
+rgf_status_t rgf_plan_destroy(rgf_plan_t plan);
+
+/* Sequential RGF (Algorithm 1 for w = 1; the n-diagonal sweep of Sec. 2.3 for
+ * w > 1) over all energies of the plan.  G, T, info as described above. */
+rgf_status_t rgf_solve(rgf_plan_t plan, const void* H, const void* sigma_L, const void* sigma_R,
+                       const double* energies, double eta_d, void* G, double* T, int32_t* info,
+                       void* workspace, size_t workspace_bytes, void* stream);
+
+/* DDRGF (Algorithm 2, one level): interiors of every energy are eliminated
+ * independently, separators are stitched through the reduced block-tridiagonal
+ * Schur complement (Proposition 4), solved by Algorithm 1, and the band of G is
+ * recovered (Algorithm 2, steps 4-5).  Same arguments as rgf_solve; the plan must
+ * have been created with method = RGF_METHOD_DDRGF (else RGF_ERR_PLAN_MISMATCH). */
+rgf_status_t ddrgf_solve(rgf_plan_t plan, const void* H, const void* sigma_L, const void* sigma_R,
+                         const double* energies, double eta_d, void* G, double* T, int32_t* info,
+                         void* workspace, size_t workspace_bytes, void* stream);
+
+/* Static text of a status code. */
+const char* rgf_status_string(rgf_status_t status);
+
+/* Library version as 10000*major + 100*minor + patch. */
+int rgf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RGF_MI355X_H */

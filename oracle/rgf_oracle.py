@@ -139,7 +139,7 @@ def dense_selected(H, w, E, sigma_L, sigma_R, eta_d=0.0, full: bool = False):
 # ----------------------------------------------------------------------------
 
 def rgf(H, E, sigma_L, sigma_R, eta_d=0.0, counter: Optional[OpCounter] = None,
-        extras: bool = True) -> Dict[str, np.ndarray]:
+        extras: bool = True, pivot_cond: bool = False) -> Dict[str, np.ndarray]:
     """Sequential RGF, w = 1.
 
     Upward pass (eliminate layer l-1 first, then l-2, ... 0): the Schur pivot of the
@@ -148,6 +148,8 @@ def rgf(H, E, sigma_L, sigma_R, eta_d=0.0, counter: Optional[OpCounter] = None,
     are obtained by solves with the LU of S_{i+1}, and S_i = M_ii - M_{i,i+1} L_{i+1}.
     Downward pass: G_00 = S_0^{-1}; for i >= 1, G_{i-1,i} = -G_{i-1,i-1} U_i,
     G_{i,i-1} = -L_i G_{i-1,i-1}, G_ii = S_i^{-1} - L_i G_{i-1,i}.
+
+    ``pivot_cond`` also returns max_i kappa_1(S_i) (see :func:`nrgf`).
 
     With ``extras`` also the first block row/column and last block row/column of
     G = M^{-1}, propagated with the same multipliers (these are the far-corner
@@ -179,6 +181,8 @@ def rgf(H, E, sigma_L, sigma_R, eta_d=0.0, counter: Optional[OpCounter] = None,
         G[0, i] = -ops.gemm(L[i], G[1, i - 1])              # G_{i,i-1}
         G[1, i] = ops.solve_left(lu[i], eye) - ops.gemm(L[i], G[2, i - 1])
     out = {"G": G}
+    if pivot_cond:
+        out["pivot_cond"] = max(_pivot_kappa(lu[i], b) for i in range(l))
     if not extras:
         return out
 

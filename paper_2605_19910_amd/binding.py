@@ -1,0 +1,163 @@
+"""Thin ctypes binding of the C ABI in include/rgf.h (argument marshalling only).
+
+Names follow the C entry points.  Tensors are torch tensors on the GPU; only their
+device pointers cross the boundary.  Every step of the computation runs in the HIP
+library: if it is missing, loading fails loudly (there is no CPU fallback).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Tuple
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "lib", "librgf.so")
+
+RGF_OK = 0
+STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported configuration", 3: "out of host memory",
+          4: "workspace missing or too small", 5: "HIP runtime error",
+          6: "plan does not match the entry point"}
+PRECISION = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+METHOD = {"rgf": 0, "sequential": 0, "ddrgf": 1}
+
+
+class RgfDesc(ctypes.Structure):
+    _fields_ = [
+        ("num_layers", ctypes.c_int64),
+        ("block_size", ctypes.c_int64),
+        ("half_bandwidth", ctypes.c_int64),
+        ("num_energies", ctypes.c_int64),
+        ("precision", ctypes.c_int32),
+        ("method", ctypes.c_int32),
+        ("num_domains", ctypes.c_int64),
+        ("separator_layers", ctypes.c_int64),
+        ("want_transmission", ctypes.c_int32),
+        ("reserved0", ctypes.c_int32),
+        ("reserved1", ctypes.c_int64),
+    ]
+
+
+class RgfError(RuntimeError):
+    def __init__(self, fn: str, code: int):
+        super().__init__(f"{fn}: {STATUS.get(code, 'unknown status')} (code {code})")
+        self.code = code
+
+
+_lib = None
+
+_VP = ctypes.c_void_p
+_SOLVE_ARGS = [_VP, _VP, _VP, _VP, _VP, ctypes.c_double, _VP, _VP, _VP, _VP, ctypes.c_size_t, _VP]
+
+
+def load() -> ctypes.CDLL:
+    """Load the built library (build it first with __graft_entry__.build())."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing "
+                           "(run `python -c 'import __graft_entry__ as g; g.build()'`)")
+    lib = ctypes.CDLL(LIB_PATH)
+    lib.rgf_plan_create.argtypes = [ctypes.POINTER(RgfDesc), ctypes.POINTER(_VP), ctypes.POINTER(ctypes.c_size_t)]
+    lib.rgf_plan_create.restype = ctypes.c_int
+    lib.rgf_plan_destroy.argtypes = [_VP]
+    lib.rgf_plan_destroy.restype = ctypes.c_int
+    for fn in ("rgf_solve", "ddrgf_solve"):
+        f = getattr(lib, fn)
+        f.argtypes = list(_SOLVE_ARGS)
+        f.restype = ctypes.c_int
+    lib.rgf_status_string.argtypes = [ctypes.c_int]
+    lib.rgf_status_string.restype = ctypes.c_char_p
+    lib.rgf_version.argtypes = []
+    lib.rgf_version.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+class Plan:
+    """Owning wrapper of an rgf_plan_t."""
+
+    def __init__(self, l: int, b: int, w: int, ne: int, method: str = "rgf", precision: str = "fp64",
+                 domains: int = 0, separator_layers: int = 0, want_transmission: bool = True):
+        self.lib = load()
+        self.desc = RgfDesc(l, b, w, ne, PRECISION[precision], METHOD[method], domains,
+                            separator_layers, 1 if want_transmission else 0, 0, 0)
+        self.handle = _VP()
+        ws = ctypes.c_size_t(0)
+        st = self.lib.rgf_plan_create(ctypes.byref(self.desc), ctypes.byref(self.handle), ctypes.byref(ws))
+        if st != RGF_OK:
+            raise RgfError("rgf_plan_create", st)
+        self.workspace_bytes = int(ws.value)
+        self.method = method
+        self.l, self.b, self.w, self.ne = l, b, w, ne
+
+    def close(self):
+        if self.handle:
+            self.lib.rgf_plan_destroy(self.handle)
+            self.handle = _VP()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def rgf_solve(plan: Plan, H, sigma_L, sigma_R, energies, eta_d: float, G, T, info, workspace,
+              stream: int = 0) -> None:
+    st = plan.lib.rgf_solve(plan.handle, _ptr(H), _ptr(sigma_L), _ptr(sigma_R), _ptr(energies),
+                            float(eta_d), _ptr(G), _ptr(T), _ptr(info), _ptr(workspace),
+                            workspace.numel() * workspace.element_size() if workspace is not None else 0,
+                            stream)
+    if st != RGF_OK:
+        raise RgfError("rgf_solve", st)
+
+
+def ddrgf_solve(plan: Plan, H, sigma_L, sigma_R, energies, eta_d: float, G, T, info, workspace,
+                stream: int = 0) -> None:
+    st = plan.lib.ddrgf_solve(plan.handle, _ptr(H), _ptr(sigma_L), _ptr(sigma_R), _ptr(energies),
+                              float(eta_d), _ptr(G), _ptr(T), _ptr(info), _ptr(workspace),
+                              workspace.numel() * workspace.element_size() if workspace is not None else 0,
+                              stream)
+    if st != RGF_OK:
+        raise RgfError("ddrgf_solve", st)
+
+
+def solve(H, sigma_L, sigma_R, energies, eta_d: float = 0.0, method: str = "rgf",
+          precision: str = "fp64", domains: int = 0, want_transmission: bool = True,
+          plan: Optional[Plan] = None, workspace=None, out=None) -> Tuple:
+    """Allocate outputs (torch, on H's device) and run one solve on the current stream.
+
+    H: complex128 [2w+1, l, b, b]; sigma_L, sigma_R: complex128 [nE, b, b];
+    energies: float64 [nE].  Returns (G [nE, 2w+1, l, b, b], T [nE], info [nE])."""
+    import torch
+    nb, l, b, _ = H.shape
+    w = (nb - 1) // 2
+    ne = energies.shape[0]
+    for t, name in ((H, "H"), (sigma_L, "sigma_L"), (sigma_R, "sigma_R")):
+        if t.dtype != torch.complex128 or not t.is_cuda or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous complex128 GPU tensor")
+    if energies.dtype != torch.float64 or not energies.is_cuda:
+        raise ValueError("energies must be a float64 GPU tensor")
+    if plan is None:
+        plan = Plan(l, b, w, ne, method=method, precision=precision, domains=domains,
+                    want_transmission=want_transmission)
+    dev = H.device
+    if out is None:
+        G = torch.empty((ne, nb, l, b, b), dtype=torch.complex128, device=dev)
+        T = torch.empty((ne,), dtype=torch.float64, device=dev)
+        info = torch.empty((ne,), dtype=torch.int32, device=dev)
+    else:
+        G, T, info = out
+    if workspace is None:
+        workspace = torch.empty((max(plan.workspace_bytes, 1),), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    if plan.method == "ddrgf":
+        ddrgf_solve(plan, H, sigma_L, sigma_R, energies, eta_d, G, T, info, workspace, stream)
+    else:
+        rgf_solve(plan, H, sigma_L, sigma_R, energies, eta_d, G, T, info, workspace, stream)
+    return G, T, info

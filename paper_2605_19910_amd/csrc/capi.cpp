@@ -1,0 +1,119 @@
+// C ABI: plan validation, workspace layout and dispatch to the HIP kernels.
+#include <new>
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/rgf.h"
+#include "kernels.h"
+
+struct rgf_plan_s {
+  rgf_desc_t d;
+  int bp;
+  size_t ws_bytes;
+  size_t ws_chain;   // sequential sweep: workspace elements per energy
+};
+
+namespace {
+
+rgf_status_t validate(const rgf_desc_t* d) {
+  if (!d) return RGF_ERR_INVALID_ARG;
+  if (d->num_layers < 1 || d->block_size < 1 || d->num_energies < 1 || d->half_bandwidth < 1)
+    return RGF_ERR_INVALID_ARG;
+  if (d->block_size > 128) return RGF_ERR_UNSUPPORTED;
+  if (d->num_layers > 1 && d->half_bandwidth >= d->num_layers) return RGF_ERR_INVALID_ARG;
+  if (d->num_layers > (int64_t)1 << 24 || d->num_energies > (int64_t)1 << 24) return RGF_ERR_UNSUPPORTED;
+  if (d->precision != RGF_FP64) return RGF_ERR_UNSUPPORTED;
+  if (d->method != RGF_METHOD_SEQUENTIAL && d->method != RGF_METHOD_DDRGF) return RGF_ERR_INVALID_ARG;
+  if (d->half_bandwidth != 1) return RGF_ERR_UNSUPPORTED;
+  if (d->method == RGF_METHOD_DDRGF) {
+    const int64_t w = d->half_bandwidth;
+    const int64_t s1 = d->separator_layers == 0 ? w : d->separator_layers;
+    if (s1 != w) return RGF_ERR_UNSUPPORTED;
+    if (d->num_domains < 1) return RGF_ERR_INVALID_ARG;
+    if (d->num_layers - d->num_domains * s1 < d->num_domains * w) return RGF_ERR_INVALID_ARG;
+  }
+  return RGF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rgf_status_t rgf_plan_create(const rgf_desc_t* desc, rgf_plan_t* plan, size_t* workspace_bytes) {
+  if (!plan) return RGF_ERR_INVALID_ARG;
+  *plan = nullptr;
+  rgf_status_t st = validate(desc);
+  if (st != RGF_OK) return st;
+  rgf_plan_s* p = new (std::nothrow) rgf_plan_s();
+  if (!p) return RGF_ERR_OUT_OF_MEMORY;
+  p->d = *desc;
+  p->bp = rgfk::padded_block((int)desc->block_size);
+  p->ws_chain = rgfk::sweep_ws_chain_elems((int)desc->num_layers, p->bp);
+  p->ws_bytes = p->ws_chain * sizeof(double2) * (size_t)desc->num_energies;
+  if (desc->method == RGF_METHOD_DDRGF) {
+    delete p;
+    return RGF_ERR_UNSUPPORTED;
+  }
+  *plan = p;
+  if (workspace_bytes) *workspace_bytes = p->ws_bytes;
+  return RGF_OK;
+}
+
+rgf_status_t rgf_plan_destroy(rgf_plan_t plan) {
+  delete plan;
+  return RGF_OK;
+}
+
+rgf_status_t rgf_solve(rgf_plan_t plan, const void* H, const void* sigma_L, const void* sigma_R,
+                       const double* energies, double eta_d, void* G, double* T, int32_t* info,
+                       void* workspace, size_t workspace_bytes, void* stream) {
+  if (!plan) return RGF_ERR_INVALID_ARG;
+  if (plan->d.method != RGF_METHOD_SEQUENTIAL) return RGF_ERR_PLAN_MISMATCH;
+  if (!H || !sigma_L || !sigma_R || !energies || !G || !info) return RGF_ERR_INVALID_ARG;
+  if (!workspace || workspace_bytes < plan->ws_bytes) return RGF_ERR_WORKSPACE_TOO_SMALL;
+  const rgf_desc_t& d = plan->d;
+  rgfk::SweepArgs a{};
+  a.H = static_cast<const double2*>(H);
+  a.h_stride = 0;
+  a.sigL = static_cast<const double2*>(sigma_L);
+  a.sigR = static_cast<const double2*>(sigma_R);
+  a.E = energies;
+  a.eta_d = eta_d;
+  a.direct = 0;
+  a.G = static_cast<double2*>(G);
+  a.g_stride = (size_t)3 * d.num_layers * d.block_size * d.block_size;
+  a.first_row = nullptr;
+  a.T = d.want_transmission ? T : nullptr;
+  a.info = info;
+  a.ws = static_cast<double2*>(workspace);
+  a.ws_chain = plan->ws_chain;
+  a.l = (int)d.num_layers;
+  a.b = (int)d.block_size;
+  a.chains = (int)d.num_energies;
+  hipError_t e = rgfk::launch_rgf_sweep(a, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? RGF_OK : RGF_ERR_HIP;
+}
+
+rgf_status_t ddrgf_solve(rgf_plan_t plan, const void*, const void*, const void*, const double*, double,
+                         void*, double*, int32_t*, void*, size_t, void*) {
+  if (!plan) return RGF_ERR_INVALID_ARG;
+  if (plan->d.method != RGF_METHOD_DDRGF) return RGF_ERR_PLAN_MISMATCH;
+  return RGF_ERR_UNSUPPORTED;
+}
+
+const char* rgf_status_string(rgf_status_t s) {
+  switch (s) {
+    case RGF_OK: return "ok";
+    case RGF_ERR_INVALID_ARG: return "invalid argument";
+    case RGF_ERR_UNSUPPORTED: return "unsupported configuration";
+    case RGF_ERR_OUT_OF_MEMORY: return "out of host memory";
+    case RGF_ERR_WORKSPACE_TOO_SMALL: return "workspace missing or too small";
+    case RGF_ERR_HIP: return "HIP runtime error";
+    case RGF_ERR_PLAN_MISMATCH: return "plan does not match the entry point";
+  }
+  return "unknown status";
+}
+
+int rgf_version(void) { return 100; }
+
+}  // extern "C"

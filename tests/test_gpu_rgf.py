@@ -1,0 +1,150 @@
+"""GPU parity of the sequential RGF path against the FP64 oracle, through the C ABI.
+
+Tolerances (FP64 path): relative Frobenius error over all selected blocks of one
+energy <= 1e-10, and |T_gpu - T_oracle| <= 1e-10 * max(1, T).  Both sides run the
+same block elimination (no pivoting across blocks), so their difference is rounding
+amplified by the Schur pivots' conditioning kappa; at the full 256 x 128 size kappa
+reaches ~1e6-1e7 for this generator and the bound there is max(1e-10, 2 kappa u).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from workloads import make_config, make_random, make_uniform_chain, surface_sigma
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+def to_dev(wl):
+    import torch
+    d = torch.device("cuda:0")
+    return (torch.from_numpy(np.ascontiguousarray(wl.H)).to(d), torch.from_numpy(wl.sigma_L).to(d),
+            torch.from_numpy(wl.sigma_R).to(d), torch.from_numpy(wl.energies).to(d))
+
+
+def run_gpu(lib, wl, method="rgf", eta_d=None, domains=0):
+    import torch
+    H, sL, sR, E = to_dev(wl)
+    G, T, info = lib.solve(H, sL, sR, E, eta_d=wl.eta_d if eta_d is None else eta_d, method=method,
+                           domains=domains)
+    torch.cuda.synchronize()
+    return G.cpu().numpy(), T.cpu().numpy(), info.cpu().numpy()
+
+
+def mask_band(G, w):
+    """Zero the blocks outside the matrix (never written by the library)."""
+    G = G.copy()
+    l = G.shape[-3]
+    for k in range(-w, w + 1):
+        if k < 0:
+            G[..., w + k, :(-k), :, :] = 0
+        elif k > 0:
+            G[..., w + k, l - k:, :, :] = 0
+    return G
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+U64 = 2.0 ** -53
+
+
+def check_energies(wl, G, T, info, energies, eta_d=None, conditioned=False):
+    """Compare with the oracle.  ``conditioned``: the bound is max(1e-10, 2 kappa u),
+    kappa = worst Schur-pivot condition number of the energy (from the oracle), the
+    rounding amplification of a block elimination without pivoting across blocks."""
+    eta_d = wl.eta_d if eta_d is None else eta_d
+    assert np.all(info == 0), info
+    for e in energies:
+        r = oracle.rgf(wl.H, wl.energies[e], wl.sigma_L[e], wl.sigma_R[e], eta_d, extras=True,
+                       pivot_cond=conditioned)
+        ref = r["G"]
+        Tref = oracle.transmission(r["row0"][wl.l - 1], wl.sigma_L[e], wl.sigma_R[e])
+        tol = max(TOL, 2.0 * r["pivot_cond"] * U64) if conditioned else TOL
+        err = rel(mask_band(G[e], wl.w), ref)
+        assert err <= tol, (e, err, tol)
+        assert abs(T[e] - Tref) <= tol * max(1.0, abs(Tref)), (e, T[e], Tref, tol)
+
+
+def test_config1(lib):
+    wl = make_config(1)
+    G, T, info = run_gpu(lib, wl)
+    check_energies(wl, G, T, info, range(wl.ne))
+
+
+# ragged block sizes (not multiples of 16) and layer counts, one to eight tiles per side
+@pytest.mark.parametrize("l,b,ne", [(1, 5, 2), (2, 16, 2), (3, 1, 2), (7, 20, 3), (13, 37, 2),
+                                    (40, 48, 2), (9, 64, 2), (17, 81, 2), (11, 100, 2),
+                                    (6, 112, 2), (12, 128, 2), (5, 127, 2)])
+def test_ragged_sizes(lib, l, b, ne):
+    wl = make_random(l, b, 1, ne, seed=500 + l * 7 + b, eta=1e-3)
+    G, T, info = run_gpu(lib, wl)
+    check_energies(wl, G, T, info, range(ne))
+
+
+def test_device_broadening(lib):
+    wl = make_random(24, 32, 1, 3, seed=9, eta=1e-3)
+    G, T, info = run_gpu(lib, wl, eta_d=0.01)
+    check_energies(wl, G, T, info, range(3), eta_d=0.01)
+
+
+def test_config2_full_size_sampled(lib):
+    """All 64 energies of the 256-layer, 128-orbital system in the benchmark launch;
+    three of them compared block by block with the oracle."""
+    wl = make_config(2)
+    G, T, info = run_gpu(lib, wl)
+    check_energies(wl, G, T, info, [0, 33, 63], conditioned=True)
+    assert np.all(np.isfinite(T)) and np.all(T >= -1e-9) and np.all(T <= wl.b + 1e-9)
+
+
+def test_uniform_chain_full_size(lib):
+    """Uniform chain at the full size: in-band T(E) is the integer number of open
+    channels (any size), and with eta_d = eta every block has a closed form."""
+    b, l, ne = 128, 256, 64
+    wl = make_uniform_chain(l, b, ne, eta=1e-6)
+    eps = wl.meta["eps"]
+    G, T, info = run_gpu(lib, wl)
+    assert np.all(info == 0)
+    n_open = np.array([np.sum(np.abs(E - eps) < 2) for E in wl.energies])
+    assert np.max(np.abs(T - n_open)) < 1e-7
+    G, T, info = run_gpu(lib, wl, eta_d=wl.eta)
+    V = wl.meta["V"]
+    for e in (0, 21, 40, 63):
+        z = wl.energies[e] + 1j * wl.eta - eps
+        s = np.sqrt(z - 2.0) * np.sqrt(z + 2.0)
+        sig = surface_sigma(z)
+        for i in (0, 1, 100, 254, 255):
+            for k in (-1, 0, 1):
+                j = i + k
+                if not (0 <= j < l):
+                    continue
+                ex = (V * (sig ** abs(k) / s)[None, :]) @ V.conj().T
+                assert np.abs(G[e, 1 + k, i] - ex).max() <= 1e-9 * np.abs(ex).max(), (e, i, k)
+
+
+def test_singular_pivot_reported(lib):
+    """Sigma_R = 0 and H_{l-1,l-1} = E I make the first Schur pivot exactly zero."""
+    wl = make_random(6, 8, 1, 2, seed=3, eta=1e-3)
+    wl.sigma_R[0] = 0.0
+    wl.H[1, 5] = wl.energies[0] * np.eye(8)
+    G, T, info = run_gpu(lib, wl)
+    assert info[0] == 6 and info[1] == 0
+    assert np.all(np.isnan(G[0])) and np.isnan(T[0])
+    assert np.all(np.isfinite(mask_band(G[1], 1)))
+
+
+def test_nonfinite_input_reported(lib):
+    wl = make_random(5, 8, 1, 1, seed=4, eta=1e-3)
+    wl.H[1, 2, 3, 3] = np.nan
+    G, T, info = run_gpu(lib, wl)
+    assert info[0] != 0 and np.isnan(T[0])
+
+
+def test_bitwise_deterministic(lib):
+    wl = make_random(20, 48, 1, 4, seed=5, eta=1e-3)
+    G1, T1, _ = run_gpu(lib, wl)
+    G2, T2, _ = run_gpu(lib, wl)
+    assert np.array_equal(mask_band(G1, 1), mask_band(G2, 1)) and np.array_equal(T1, T2)
