@@ -50,6 +50,16 @@ def algorithmic_bytes(l: int, b: int, ne: int, w: int = 1) -> float:
 _W = None
 
 
+def _worker_init(cfg: int):
+    global _W
+    from workloads import make_config
+    _W = make_config(cfg)
+
+
+def _noop(_):
+    return 0
+
+
 def _oracle_one(e: int) -> float:
     import oracle
     wl = _W
@@ -58,17 +68,24 @@ def _oracle_one(e: int) -> float:
     return T
 
 
-def cpu_baseline(wl, n_sample: int, workers: int):
-    global _W
+def log(msg: str):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(wl, n_sample: int, workers: int, cfg: int = 2):
+    # fresh interpreters with one BLAS thread each (forking a process whose BLAS
+    # thread pool is running can deadlock); each worker regenerates the seeded input
     os.environ["OPENBLAS_NUM_THREADS"] = "1"
     os.environ["OMP_NUM_THREADS"] = "1"
-    _W = wl
     idx = list(range(min(n_sample, wl.ne)))
-    ctx = mp.get_context("fork")
-    t0 = time.perf_counter()
-    with ctx.Pool(workers) as pool:
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(workers, initializer=_worker_init, initargs=(cfg,)) as pool:
+        pool.map(_noop, range(workers), chunksize=1)
+        log(f"cpu baseline: {workers} workers ready, timing {len(idx)} oracle energies")
+        t0 = time.perf_counter()
         pool.map(_oracle_one, idx, chunksize=1)
-    dt = time.perf_counter() - t0
+        dt = time.perf_counter() - t0
+    log(f"cpu baseline: {dt:.1f} s")
     return {"value": len(idx) / dt, "unit": "energy points/s", "cores": workers, "kind": "oracle",
             "sample": f"first {len(idx)} of the {wl.ne} energies of the same system, one energy per "
                       f"worker process, {workers} processes with 1 BLAS thread each, wall {dt:.1f} s"}
@@ -123,9 +140,11 @@ def main():
     def step():
         binding.rgf_solve(plan, H, sL, sR, E, wl.eta_d, G, T, info, ws, stream.cuda_stream)
 
+    log("inputs on the GPU; warmup")
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    log("warmup done; timing")
     if not bool((info == 0).all()) or not bool(torch.isfinite(T).all()):
         print(json.dumps({"error": "solve reported a failure", "info": info.cpu().tolist()}), flush=True)
         sys.exit(1)
