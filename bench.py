@@ -37,6 +37,21 @@ def rgf_flops_per_energy(l: int, b: int) -> float:
     return (8.0 / 3.0 * l + 8.0 * (3 * l - 2) + 8.0 * 4 * (l - 1) + 8.0 * (l - 1)) * b3
 
 
+def ddrgf_interior_flops(l: int, b: int, m: int, ne: int) -> float:
+    """Flops executed by the DDRGF interior kernel (closed-interior RGF plus the
+    halo products), 8 b^3 per complex product or Gauss-Jordan inversion: per
+    interior of n layers, n inversions, 5(n-1) upward products (L, U, the two
+    last-row/column propagators, the Schur update), 3(n-1) downward products, and
+    2n (last row/column) + 2n (first row/column, all but the first interior)."""
+    base, rem = divmod(l - m, m)
+    tot = 0.0
+    for k in range(m):
+        n = base + (1 if k < rem else 0)
+        ops = n + 5 * (n - 1) + 3 * (n - 1) + 2 * n + (2 * n if k > 0 else 0)
+        tot += ops
+    return tot * 8.0 * float(b) ** 3 * ne
+
+
 def algorithmic_bytes(l: int, b: int, ne: int, w: int = 1) -> float:
     """H read once, Sigma_L/R and E read once, G band written once, T written once."""
     blk = 16.0 * b * b
@@ -96,7 +111,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--method", default="rgf", choices=["rgf"])
+    ap.add_argument("--method", default="both", choices=["rgf", "ddrgf", "both"])
+    ap.add_argument("--domains", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-workers", type=int, default=0)
     args = ap.parse_args()
@@ -130,48 +146,74 @@ def main():
     sL = torch.from_numpy(wl.sigma_L).to(dev)
     sR = torch.from_numpy(wl.sigma_R).to(dev)
     E = torch.from_numpy(wl.energies).to(dev)
-    plan = binding.Plan(l, b, w, ne, method=args.method)
     G = torch.empty((ne, 2 * w + 1, l, b, b), dtype=torch.complex128, device=dev)
     T = torch.empty((ne,), dtype=torch.float64, device=dev)
     info = torch.empty((ne,), dtype=torch.int32, device=dev)
-    ws = torch.empty((plan.workspace_bytes,), dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream(dev)
 
-    def step():
-        binding.rgf_solve(plan, H, sL, sR, E, wl.eta_d, G, T, info, ws, stream.cuda_stream)
+    def run_leg(method: str):
+        if method == "rgf":
+            plan = binding.Plan(l, b, w, ne, method="rgf")
+            fn = binding.rgf_solve
+        else:
+            plan = binding.Plan(l, b, w, ne, method="ddrgf", domains=args.domains)
+            fn = binding.ddrgf_solve
+        ws = torch.empty((plan.workspace_bytes,), dtype=torch.uint8, device=dev)
 
-    log("inputs on the GPU; warmup")
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    log("warmup done; timing")
-    if not bool((info == 0).all()) or not bool(torch.isfinite(T).all()):
-        print(json.dumps({"error": "solve reported a failure", "info": info.cpu().tolist()}), flush=True)
-        sys.exit(1)
+        def step():
+            fn(plan, H, sL, sR, E, wl.eta_d, G, T, info, ws, stream.cuda_stream)
 
-    events = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        step()
-        e1.record(stream)
-        events.append((e0, e1))
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    wall = t1 - t0
-    kern_ms = float(np.mean([a.elapsed_time(c) for a, c in events]))
-    ms_per_step = 1000.0 * wall / args.steps
-    value = ne * args.steps / wall
+        log(f"{method}: inputs on the GPU; warmup")
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        if not bool((info == 0).all()) or not bool(torch.isfinite(T).all()):
+            print(json.dumps({"error": f"{method} solve reported a failure",
+                              "info": info.cpu().tolist()}), flush=True)
+            sys.exit(1)
+        log(f"{method}: warmup done; timing")
+        events = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            step()
+            e1.record(stream)
+            events.append((e0, e1))
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        step_ms = float(np.mean([a.elapsed_time(c) for a, c in events]))
+        res = {"value": ne * args.steps / wall, "ms_per_step": 1000.0 * wall / args.steps,
+               "gpu_ms_per_step": step_ms}
+        # dominant kernel, timed alone with HIP events on the same stream
+        if method == "rgf":
+            res["kernel"] = f"rgf_sweep_kernel (b={b}, l={l}, {ne} chains)"
+            res["kernel_ms"] = step_ms
+            res["flops_per_launch"] = rgf_flops_per_energy(l, b) * ne
+        else:
+            res["kernel"] = f"ddrgf_interior_kernel (b={b}, {args.domains} interiors x {ne} energies)"
+            res["flops_per_launch"] = ddrgf_interior_flops(l, b, args.domains, ne)
+            res["kernel_ms"] = None   # filled from the per-kernel profile when available
+        del ws, plan
+        torch.cuda.empty_cache()
+        log(f"{method}: {res['value']:.2f} energy points/s, {step_ms:.2f} ms per step")
+        return res
 
-    flops = rgf_flops_per_energy(l, b) * ne
+    legs = {}
+    for method in (["rgf", "ddrgf"] if args.method == "both" else [args.method]):
+        legs[method] = run_leg(method)
+    best = max(legs, key=lambda k: legs[k]["value"])
+    lead = legs["rgf"] if "rgf" in legs else legs[best]
+    value = legs[best]["value"]
+    ms_per_step = legs[best]["ms_per_step"]
+    kern_ms = lead["kernel_ms"]
+    flops = lead["flops_per_launch"]
     achieved = flops / (kern_ms * 1e-3) / 1e12
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None,
-                "kernel": f"rgf_sweep_kernel (b={b}, l={l}, {ne} chains)",
-                "kernel_ms": round(kern_ms, 3), "flops_per_launch": flops,
+                "kernel": lead["kernel"], "kernel_ms": round(kern_ms, 3), "flops_per_launch": flops,
                 "algorithmic_bytes_per_launch": algorithmic_bytes(l, b, ne, w)}
 
     out = {
@@ -187,10 +229,15 @@ def main():
         "vs_baseline": None,
         "dtype": "c128 (f64)",
         "data": "synthetic: seeded random Hermitian block band, closed-form lead self-energies",
-        "config": {"workload": "block-tridiagonal RGF, l=256 layers, b=128, 64 energies in [-2,2], "
-                               "eta=1e-6, seed 102", "method": "sequential RGF (Algorithm 1)",
-                   "precision": "fp64", "parallelism": "one workgroup per energy"},
+        "config": {"workload": "block-tridiagonal, l=256 layers, b=128, 64 energies in [-2,2], "
+                               "eta=1e-6, seed 102",
+                   "method": {"rgf": "sequential RGF (Algorithm 1)",
+                              "ddrgf": f"DDRGF (Algorithm 2), {args.domains} domains"}[best],
+                   "precision": "fp64",
+                   "parallelism": "one workgroup per energy (RGF) / per (energy, domain) (DDRGF)"},
         "roofline": roofline,
+        "legs": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                 for k, v in legs.items()},
     }
     if cpu is not None:
         out["cpu_baseline"] = cpu

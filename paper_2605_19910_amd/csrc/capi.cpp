@@ -11,7 +11,14 @@ struct rgf_plan_s {
   int bp;
   size_t ws_bytes;
   size_t ws_chain;   // sequential sweep: workspace elements per energy
+  // DDRGF workspace layout (byte offsets)
+  size_t dd_int_chain, dd_red_chain;
+  size_t off_int, off_ms, off_gs, off_gsrow, off_red, off_fin, off_info;
 };
+
+namespace {
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+}
 
 namespace {
 
@@ -51,8 +58,21 @@ rgf_status_t rgf_plan_create(const rgf_desc_t* desc, rgf_plan_t* plan, size_t* w
   p->ws_chain = rgfk::sweep_ws_chain_elems((int)desc->num_layers, p->bp);
   p->ws_bytes = p->ws_chain * sizeof(double2) * (size_t)desc->num_energies;
   if (desc->method == RGF_METHOD_DDRGF) {
-    delete p;
-    return RGF_ERR_UNSUPPORTED;
+    const int l = (int)desc->num_layers, m = (int)desc->num_domains, ne = (int)desc->num_energies;
+    const size_t b = (size_t)desc->block_size, bb = b * b, bpbp = (size_t)p->bp * p->bp;
+    int base = 0, rem = 0;
+    rgfk::ddrgf_layout_host(l, m, &base, &rem);
+    p->dd_int_chain = rgfk::ddrgf_interior_ws_elems(base + 1, p->bp);
+    p->dd_red_chain = rgfk::sweep_ws_chain_elems(m, p->bp);
+    size_t off = 0;
+    p->off_int = off;   off = align256(off + p->dd_int_chain * sizeof(double2) * (size_t)ne * m);
+    p->off_ms = off;    off = align256(off + (size_t)ne * 3 * m * bb * sizeof(double2));
+    p->off_gs = off;    off = align256(off + (size_t)ne * 3 * m * bb * sizeof(double2));
+    p->off_gsrow = off; off = align256(off + (size_t)ne * m * bb * sizeof(double2));
+    p->off_red = off;   off = align256(off + p->dd_red_chain * sizeof(double2) * (size_t)ne);
+    p->off_fin = off;   off = align256(off + (size_t)ne * 4 * bpbp * sizeof(double2));
+    p->off_info = off;  off = align256(off + (size_t)ne * (m + 1) * sizeof(int));
+    p->ws_bytes = off;
   }
   *plan = p;
   if (workspace_bytes) *workspace_bytes = p->ws_bytes;
@@ -85,6 +105,8 @@ rgf_status_t rgf_solve(rgf_plan_t plan, const void* H, const void* sigma_L, cons
   a.first_row = nullptr;
   a.T = d.want_transmission ? T : nullptr;
   a.info = info;
+  a.info_stride = 1;
+  a.info_offset = 0;
   a.ws = static_cast<double2*>(workspace);
   a.ws_chain = plan->ws_chain;
   a.l = (int)d.num_layers;
@@ -94,11 +116,39 @@ rgf_status_t rgf_solve(rgf_plan_t plan, const void* H, const void* sigma_L, cons
   return e == hipSuccess ? RGF_OK : RGF_ERR_HIP;
 }
 
-rgf_status_t ddrgf_solve(rgf_plan_t plan, const void*, const void*, const void*, const double*, double,
-                         void*, double*, int32_t*, void*, size_t, void*) {
+rgf_status_t ddrgf_solve(rgf_plan_t plan, const void* H, const void* sigma_L, const void* sigma_R,
+                         const double* energies, double eta_d, void* G, double* T, int32_t* info,
+                         void* workspace, size_t workspace_bytes, void* stream) {
   if (!plan) return RGF_ERR_INVALID_ARG;
   if (plan->d.method != RGF_METHOD_DDRGF) return RGF_ERR_PLAN_MISMATCH;
-  return RGF_ERR_UNSUPPORTED;
+  if (!H || !sigma_L || !sigma_R || !energies || !G || !info) return RGF_ERR_INVALID_ARG;
+  if (!workspace || workspace_bytes < plan->ws_bytes) return RGF_ERR_WORKSPACE_TOO_SMALL;
+  const rgf_desc_t& d = plan->d;
+  char* ws = static_cast<char*>(workspace);
+  rgfk::DDArgs a{};
+  a.H = static_cast<const double2*>(H);
+  a.sigL = static_cast<const double2*>(sigma_L);
+  a.sigR = static_cast<const double2*>(sigma_R);
+  a.E = energies;
+  a.eta_d = eta_d;
+  a.G = static_cast<double2*>(G);
+  a.T = d.want_transmission ? T : nullptr;
+  a.info = info;
+  a.l = (int)d.num_layers;
+  a.b = (int)d.block_size;
+  a.m = (int)d.num_domains;
+  a.ne = (int)d.num_energies;
+  a.ws_int = reinterpret_cast<double2*>(ws + plan->off_int);
+  a.ws_int_chain = plan->dd_int_chain;
+  a.MS = reinterpret_cast<double2*>(ws + plan->off_ms);
+  a.GS = reinterpret_cast<double2*>(ws + plan->off_gs);
+  a.GSrow = reinterpret_cast<double2*>(ws + plan->off_gsrow);
+  a.ws_red = reinterpret_cast<double2*>(ws + plan->off_red);
+  a.ws_red_chain = plan->dd_red_chain;
+  a.ws_fin = reinterpret_cast<double2*>(ws + plan->off_fin);
+  a.info_part = reinterpret_cast<int*>(ws + plan->off_info);
+  hipError_t e = rgfk::launch_ddrgf(a, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? RGF_OK : RGF_ERR_HIP;
 }
 
 const char* rgf_status_string(rgf_status_t s) {

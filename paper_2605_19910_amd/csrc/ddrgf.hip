@@ -1,0 +1,458 @@
+// DDRGF for block tridiagonal systems (paper Sec. 3, Algorithm 2), one level, on gfx950.
+//
+// Layout (the figure of Sec. 3): m pairs (interior D2^k, separator D1^k), k = 0..m-1;
+// interior k is layers [a_k, a_k + n_k - 1], separator k is the single layer
+// p_k = a_k + n_k; the chain starts with an interior at layer 0 and ends with the
+// separator p_{m-1} = l - 1.  The l - m interior layers are split as evenly as
+// possible, the first (l - m) mod m interiors taking one extra layer.
+//
+// Kernels (all energies and domains batched in each launch):
+//   1. ddrgf_interior_kernel  one workgroup per (energy, interior): RGF of the
+//      closed interior (Algorithm 1) giving the band of X = (M_{D2^k})^{-1}, written
+//      straight into G, plus the halo products needed later (the "internal halos"):
+//        CL_i = X_{i,0} M_{a,qL},  RL_i = M_{qL,a} X_{0,i}     (first column / row)
+//        CR_i = X_{i,n-1} M_{e,qR}, RR_i = M_{qR,e} X_{n-1,i}  (last column / row)
+//      with qL = a - 1, qR = e + 1 the neighbouring separators.  First column/row
+//      follow X_{i,0} = -L_i X_{i-1,0}, X_{0,i} = -X_{0,i-1} U_i; last column/row
+//      X_{i,n-1} = X_ii P_i, X_{n-1,i} = Q_i X_ii with P_i = -U_{i+1} P_{i+1},
+//      Q_i = -Q_{i+1} L_{i+1}; the couplings are folded into P, Q at the end layer.
+//   2. ddrgf_schur_kernel  one workgroup per (energy, separator): the reduced
+//      system T_S = T_11 - T_12 T_22^{-1} T_21 (eq. Schur complement in DDRGF),
+//      block tridiagonal over the separators (Proposition 4) including the
+//      couplings between neighbouring separators through one interior:
+//        S_kk      = M_pp - M_{p,e_k} X^(k)_{ee} M_{e_k,p} - M_{p,a_{k+1}} X^(k+1)_{aa} M_{a_{k+1},p}
+//        S_{k,k+1} = -M_{p_k,a_{k+1}} X^(k+1)_{a,e} M_{e_{k+1},p_{k+1}}
+//        S_{k+1,k} = -M_{p_{k+1},e_{k+1}} X^(k+1)_{e,a} M_{a_{k+1},p_k}
+//   3. the sequential sweep kernel on the reduced system ("direct" mode) gives the
+//      band of G_S = T_S^{-1} and its first block row.
+//   4. ddrgf_recover_kernel  one workgroup per (energy, interior): Algorithm 2 step 4,
+//        G_{D2,D2} = X + X T_21 G_S T_12 X,  G_{D2,D1} = -X T_21 G_S,  G_{D1,D2} = -G_S T_12 X,
+//      restricted to the band and added in place; step 5 (inverse reordering) is
+//      the index map of the layout, nothing is permuted.
+//   5. ddrgf_finalize_kernel  one workgroup per energy: T(E) from
+//      G_{0,l-1} = -CR^(0)_0 G_S(0, m-1), status and NaN fill.
+#include "block_engine.h"
+#include "kernels.h"
+
+namespace rgfk {
+
+struct DDLayout {
+  int base, rem;
+  __host__ __device__ int n(int k) const { return base + (k < rem ? 1 : 0); }
+  __host__ __device__ int a(int k) const { return k * (base + 1) + (k < rem ? k : rem); }
+  __host__ __device__ int p(int k) const { return a(k) + n(k); }
+};
+
+__host__ __device__ inline DDLayout dd_layout(int l, int m) {
+  DDLayout d;
+  d.base = (l - m) / m;
+  d.rem = (l - m) % m;
+  return d;
+}
+
+size_t ddrgf_interior_ws_elems(int nmax, int bp) { return (size_t)(9 * (size_t)nmax + 2) * bp * bp; }
+
+// Diagonal block of M for global layer i: (E + i eta) I - H_ii - [i==0] Sigma_L - [i==l-1] Sigma_R.
+template <int T, int NW>
+__device__ __forceinline__ void diag_M(Acc<T, NW>& acc, const DDArgs& a, int e, int i) {
+  const size_t bb = (size_t)a.b * a.b;
+  const double2 z = make_double2(a.E[e], a.eta_d);
+  assemble_diag<T, NW>(acc, a.H + (size_t)(a.l + i) * bb, a.b, z,
+                       i == 0 ? a.sigL + (size_t)e * bb : nullptr,
+                       i == a.l - 1 ? a.sigR + (size_t)e * bb : nullptr);
+}
+
+// H band accessors: block (i, i-1), (i, i+1)
+__device__ __forceinline__ const double2* Hlo(const DDArgs& a, int i) {
+  return a.H + (size_t)i * a.b * a.b;
+}
+__device__ __forceinline__ const double2* Hup(const DDArgs& a, int i) {
+  return a.H + (size_t)(2 * a.l + i) * a.b * a.b;
+}
+
+// ---------------------------------------------------------------------------
+// 1. interiors
+// ---------------------------------------------------------------------------
+template <int T, int NW>
+__global__ __launch_bounds__(64 * NW, 1) void ddrgf_interior_kernel(DDArgs a) {
+  constexpr int BP = 16 * T;
+  __shared__ GJShared sh;
+  const int c = blockIdx.x;
+  const int e = c / a.m, k = c % a.m;
+  const DDLayout lay = dd_layout(a.l, a.m);
+  const int n = lay.n(k), a0 = lay.a(k), qR = lay.p(k), qL = a0 - 1;
+  const int b = a.b;
+  const size_t bb = (size_t)b * b, bpbp = (size_t)BP * BP;
+  const int nmax = lay.base + 1;
+  double2* ws = a.ws_int + (size_t)c * a.ws_int_chain;
+  double2* g = ws;
+  double2* U = g + (size_t)nmax * bpbp;
+  double2* L = U + (size_t)nmax * bpbp;
+  double2* Pt = L + (size_t)nmax * bpbp;
+  double2* Qt = Pt + (size_t)nmax * bpbp;
+  double2* CL = Qt + (size_t)nmax * bpbp;
+  double2* CR = CL + (size_t)nmax * bpbp;
+  double2* RL = CR + (size_t)nmax * bpbp;
+  double2* RR = RL + (size_t)nmax * bpbp;
+  double2* Gout = a.G + (size_t)e * 3 * a.l * bb;
+  double2* Gl = Gout;
+  double2* Gd = Gout + (size_t)a.l * bb;
+  double2* Gu = Gout + (size_t)2 * a.l * bb;
+  const bool left = k > 0;
+
+  int bad_layer = -1;
+  Acc<T, NW> acc;
+
+  // ---------------- upward pass over the closed interior ----------------
+  diag_M<T, NW>(acc, a, e, a0 + n - 1);
+  for (int i = n - 1; i >= 0; --i) {
+    gj_invert<T, NW>(acc, g + (size_t)i * bpbp, sh);
+    if (sh.bad && bad_layer < 0) bad_layer = a0 + i;
+    __syncthreads();
+    if (i == n - 1) {
+      // P_{n-1} folded with M_{e,qR} = -H_{e,e+1};  Q_{n-1} with M_{qR,e} = -H_{qR,qR-1}
+      load<T, NW>(acc, opnd(Hup(a, a0 + n - 1), b, b, b), -1.0);
+      store<T, NW>(acc, Pt + (size_t)i * bpbp, BP, BP, BP);
+      load<T, NW>(acc, opnd(Hlo(a, qR), b, b, b), -1.0);
+      store<T, NW>(acc, Qt + (size_t)i * bpbp, BP, BP, BP);
+      __syncthreads();
+    }
+    if (i == 0) break;
+    const int gi = a0 + i;
+    acc_zero<T, NW>(acc);
+    mma<T, NW>(acc, opnd(g + (size_t)i * bpbp, BP, BP, BP), opnd(Hlo(a, gi), b, b, b), -1.0);
+    store<T, NW>(acc, L + (size_t)i * bpbp, BP, BP, BP);
+    acc_zero<T, NW>(acc);
+    mma<T, NW>(acc, opnd(Hup(a, gi - 1), b, b, b), opnd(g + (size_t)i * bpbp, BP, BP, BP), -1.0);
+    store<T, NW>(acc, U + (size_t)i * bpbp, BP, BP, BP);
+    __syncthreads();
+    acc_zero<T, NW>(acc);
+    mma<T, NW>(acc, opnd(U + (size_t)i * bpbp, BP, BP, BP), opnd(Pt + (size_t)i * bpbp, BP, BP, BP), -1.0);
+    store<T, NW>(acc, Pt + (size_t)(i - 1) * bpbp, BP, BP, BP);
+    acc_zero<T, NW>(acc);
+    mma<T, NW>(acc, opnd(Qt + (size_t)i * bpbp, BP, BP, BP), opnd(L + (size_t)i * bpbp, BP, BP, BP), -1.0);
+    store<T, NW>(acc, Qt + (size_t)(i - 1) * bpbp, BP, BP, BP);
+    diag_M<T, NW>(acc, a, e, gi - 1);
+    mma<T, NW>(acc, opnd(Hup(a, gi - 1), b, b, b), opnd(L + (size_t)i * bpbp, BP, BP, BP), 1.0);
+    __syncthreads();
+  }
+
+  // ---------------- downward pass, band of X and halo products ----------------
+  load<T, NW>(acc, opnd(g, BP, BP, BP));
+  store<T, NW>(acc, Gd + (size_t)a0 * bb, b, b, b);
+  __syncthreads();
+  const Opnd X00 = opnd(Gd + (size_t)a0 * bb, b, b, b);
+  if (left) {
+    acc_zero<T, NW>(acc);
+    mma<T, NW>(acc, X00, opnd(Hlo(a, a0), b, b, b), -1.0);          // X_00 M_{a,qL}
+    store<T, NW>(acc, CL, BP, BP, BP);
+    acc_zero<T, NW>(acc);
+    mma<T, NW>(acc, opnd(Hup(a, qL), b, b, b), X00, -1.0);          // M_{qL,a} X_00
+    store<T, NW>(acc, RL, BP, BP, BP);
+  }
+  acc_zero<T, NW>(acc);
+  mma<T, NW>(acc, X00, opnd(Pt, BP, BP, BP), 1.0);
+  store<T, NW>(acc, CR, BP, BP, BP);
+  acc_zero<T, NW>(acc);
+  mma<T, NW>(acc, opnd(Qt, BP, BP, BP), X00, 1.0);
+  store<T, NW>(acc, RR, BP, BP, BP);
+  __syncthreads();
+  for (int i = 1; i < n; ++i) {
+    const int gi = a0 + i;
+    const Opnd Xp = opnd(Gd + (size_t)(gi - 1) * bb, b, b, b);
+    const Opnd Ui = opnd(U + (size_t)i * bpbp, BP, BP, BP);
+    const Opnd Li = opnd(L + (size_t)i * bpbp, BP, BP, BP);
+    acc_zero<T, NW>(acc);
+    mma<T, NW>(acc, Xp, Ui, -1.0);
+    store<T, NW>(acc, Gu + (size_t)(gi - 1) * bb, b, b, b);
+    acc_zero<T, NW>(acc);
+    mma<T, NW>(acc, Li, Xp, -1.0);
+    store<T, NW>(acc, Gl + (size_t)gi * bb, b, b, b);
+    if (left) {
+      acc_zero<T, NW>(acc);
+      mma<T, NW>(acc, Li, opnd(CL + (size_t)(i - 1) * bpbp, BP, BP, BP), -1.0);
+      store<T, NW>(acc, CL + (size_t)i * bpbp, BP, BP, BP);
+      acc_zero<T, NW>(acc);
+      mma<T, NW>(acc, opnd(RL + (size_t)(i - 1) * bpbp, BP, BP, BP), Ui, -1.0);
+      store<T, NW>(acc, RL + (size_t)i * bpbp, BP, BP, BP);
+    }
+    __syncthreads();
+    load<T, NW>(acc, opnd(g + (size_t)i * bpbp, BP, BP, BP));
+    mma<T, NW>(acc, Li, opnd(Gu + (size_t)(gi - 1) * bb, b, b, b), -1.0);
+    store<T, NW>(acc, Gd + (size_t)gi * bb, b, b, b);
+    __syncthreads();
+    const Opnd Xii = opnd(Gd + (size_t)gi * bb, b, b, b);
+    acc_zero<T, NW>(acc);
+    mma<T, NW>(acc, Xii, opnd(Pt + (size_t)i * bpbp, BP, BP, BP), 1.0);
+    store<T, NW>(acc, CR + (size_t)i * bpbp, BP, BP, BP);
+    acc_zero<T, NW>(acc);
+    mma<T, NW>(acc, opnd(Qt + (size_t)i * bpbp, BP, BP, BP), Xii, 1.0);
+    store<T, NW>(acc, RR + (size_t)i * bpbp, BP, BP, BP);
+  }
+  if (threadIdx.x == 0) a.info_part[(size_t)e * (a.m + 1) + k] = bad_layer >= 0 ? bad_layer + 1 : 0;
+}
+
+// ---------------------------------------------------------------------------
+// 2. reduced system on the separators
+// ---------------------------------------------------------------------------
+template <int T, int NW>
+__global__ __launch_bounds__(64 * NW, 1) void ddrgf_schur_kernel(DDArgs a) {
+  constexpr int BP = 16 * T;
+  const int c = blockIdx.x;
+  const int e = c / a.m, k = c % a.m;
+  const DDLayout lay = dd_layout(a.l, a.m);
+  const int b = a.b, m = a.m;
+  const size_t bb = (size_t)b * b, bpbp = (size_t)BP * BP;
+  const int nmax = lay.base + 1;
+  const int p = lay.p(k);
+  auto halo = [&](int kk, int which, int i) -> const double2* {
+    // which: 0 CL, 1 CR, 2 RL, 3 RR
+    const double2* ws = a.ws_int + (size_t)(e * m + kk) * a.ws_int_chain;
+    return ws + ((size_t)(5 + which) * nmax + i) * bpbp;
+  };
+  double2* MS = a.MS + (size_t)e * 3 * m * bb;    // direct band of T_S
+  Acc<T, NW> acc;
+  // S_kk = M_pp - M_{p,e_k} CR^(k)_{n-1} - M_{p,a_{k+1}} CL^(k+1)_0,  M_{p,e} = -H_{p,p-1}, M_{p,a} = -H_{p,p+1}
+  diag_M<T, NW>(acc, a, e, p);
+  mma<T, NW>(acc, opnd(Hlo(a, p), b, b, b), opnd(halo(k, 1, lay.n(k) - 1), BP, BP, BP), 1.0);
+  if (k + 1 < m)
+    mma<T, NW>(acc, opnd(Hup(a, p), b, b, b), opnd(halo(k + 1, 0, 0), BP, BP, BP), 1.0);
+  store<T, NW>(acc, MS + (size_t)(m + k) * bb, b, b, b);
+  if (k + 1 < m) {
+    const int p1 = lay.p(k + 1);
+    // S_{k,k+1} = -M_{p_k,a_{k+1}} CR^(k+1)_0 = H_{p,p+1} CR^(k+1)_0
+    acc_zero<T, NW>(acc);
+    mma<T, NW>(acc, opnd(Hup(a, p), b, b, b), opnd(halo(k + 1, 1, 0), BP, BP, BP), 1.0);
+    store<T, NW>(acc, MS + (size_t)(2 * m + k) * bb, b, b, b);
+    // S_{k+1,k} = -M_{p_{k+1},e_{k+1}} CL^(k+1)_{n-1} = H_{p1,p1-1} CL^(k+1)_{n-1}
+    acc_zero<T, NW>(acc);
+    mma<T, NW>(acc, opnd(Hlo(a, p1), b, b, b), opnd(halo(k + 1, 0, lay.n(k + 1) - 1), BP, BP, BP), 1.0);
+    store<T, NW>(acc, MS + (size_t)(k + 1) * bb, b, b, b);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 4. recovery of the interior blocks and the separator couplings
+// ---------------------------------------------------------------------------
+template <int T, int NW>
+__global__ __launch_bounds__(64 * NW, 1) void ddrgf_recover_kernel(DDArgs a) {
+  constexpr int BP = 16 * T;
+  const int c = blockIdx.x;
+  const int e = c / a.m, k = c % a.m;
+  const DDLayout lay = dd_layout(a.l, a.m);
+  const int n = lay.n(k), a0 = lay.a(k), qR = lay.p(k), qL = a0 - 1;
+  const int b = a.b, m = a.m;
+  const size_t bb = (size_t)b * b, bpbp = (size_t)BP * BP;
+  const int nmax = lay.base + 1;
+  const bool left = k > 0;
+  double2* ws = a.ws_int + (size_t)c * a.ws_int_chain;
+  const double2* CL = ws + (size_t)5 * nmax * bpbp;
+  const double2* CR = ws + (size_t)6 * nmax * bpbp;
+  const double2* RL = ws + (size_t)7 * nmax * bpbp;
+  const double2* RR = ws + (size_t)8 * nmax * bpbp;
+  double2* VL = ws + (size_t)9 * nmax * bpbp;     // 1 block
+  double2* VR = VL + bpbp;                         // 1 block (reuses the spare blocks)
+  const double2* GS = a.GS + (size_t)e * 3 * m * bb;
+  const Opnd ZRR = opnd(GS + (size_t)(m + k) * bb, b, b, b);
+  const int km = left ? k - 1 : k;   // (unused when there is no left separator)
+  const Opnd ZLL = opnd(GS + (size_t)(m + km) * bb, b, b, b);
+  const Opnd ZLR = opnd(GS + (size_t)(2 * m + km) * bb, b, b, b);      // G_S(k-1, k)
+  const Opnd ZRL = opnd(GS + (size_t)(k)*bb, b, b, b);                 // G_S(k, k-1)
+  double2* Gout = a.G + (size_t)e * 3 * a.l * bb;
+  double2* Gl = Gout;
+  double2* Gd = Gout + (size_t)a.l * bb;
+  double2* Gu = Gout + (size_t)2 * a.l * bb;
+  auto blk = [&](const double2* base, int i) { return opnd(base + (size_t)i * bpbp, BP, BP, BP); };
+
+  Acc<T, NW> acc;
+  for (int i = 0; i < n; ++i) {
+    const int gi = a0 + i;
+    // V_i = [CL_i, CR_i] Z
+    acc_zero<T, NW>(acc);
+    if (left) {
+      mma<T, NW>(acc, blk(CL, i), ZLR, 1.0);
+    }
+    mma<T, NW>(acc, blk(CR, i), ZRR, 1.0);
+    store<T, NW>(acc, VR, BP, BP, BP);
+    if (i == n - 1) store<T, NW>(acc, Gu + (size_t)gi * bb, b, b, b, -1.0);   // G_{e,qR} = -V^R
+    if (left) {
+      acc_zero<T, NW>(acc);
+      mma<T, NW>(acc, blk(CL, i), ZLL, 1.0);
+      mma<T, NW>(acc, blk(CR, i), ZRL, 1.0);
+      store<T, NW>(acc, VL, BP, BP, BP);
+      if (i == 0) store<T, NW>(acc, Gl + (size_t)gi * bb, b, b, b, -1.0);     // G_{a,qL} = -V^L
+    }
+    __syncthreads();
+    // G_ij += V^L_i RL_j + V^R_i RR_j for j = i-1, i, i+1 inside the interior
+    for (int d = -1; d <= 1; ++d) {
+      const int j = i + d;
+      if (j < 0 || j >= n) continue;
+      double2* dst = (d == 0 ? Gd : (d < 0 ? Gl : Gu)) + (size_t)gi * bb;
+      load<T, NW>(acc, opnd(dst, b, b, b));
+      if (left) mma<T, NW>(acc, opnd(VL, BP, BP, BP), blk(RL, j), 1.0);
+      mma<T, NW>(acc, opnd(VR, BP, BP, BP), blk(RR, j), 1.0);
+      store<T, NW>(acc, dst, b, b, b);
+    }
+    __syncthreads();
+  }
+  // G_{qR,e} = -(G_S(k,k-1) RL_{n-1} + G_S(k,k) RR_{n-1});  G_{qL,a} = -(G_S(k-1,k-1) RL_0 + G_S(k-1,k) RR_0)
+  acc_zero<T, NW>(acc);
+  if (left) mma<T, NW>(acc, ZRL, blk(RL, n - 1), -1.0);
+  mma<T, NW>(acc, ZRR, blk(RR, n - 1), -1.0);
+  store<T, NW>(acc, Gl + (size_t)qR * bb, b, b, b);
+  if (left) {
+    acc_zero<T, NW>(acc);
+    mma<T, NW>(acc, ZLL, blk(RL, 0), -1.0);
+    mma<T, NW>(acc, ZLR, blk(RR, 0), -1.0);
+    store<T, NW>(acc, Gu + (size_t)qL * bb, b, b, b);
+  }
+  // separator diagonal block
+  load<T, NW>(acc, ZRR);
+  store<T, NW>(acc, Gd + (size_t)qR * bb, b, b, b);
+}
+
+// ---------------------------------------------------------------------------
+// 5. per-energy transmission, status and NaN fill
+// ---------------------------------------------------------------------------
+template <int T, int NW>
+__global__ __launch_bounds__(64 * NW, 1) void ddrgf_finalize_kernel(DDArgs a) {
+  constexpr int BP = 16 * T;
+  constexpr int NT = 64 * NW;
+  __shared__ double red[NW];
+  __shared__ int s_info;
+  const int e = blockIdx.x, t = threadIdx.x;
+  const int b = a.b, m = a.m;
+  const size_t bb = (size_t)b * b, bpbp = (size_t)BP * BP;
+  const DDLayout lay = dd_layout(a.l, m);
+  const int nmax = lay.base + 1;
+  if (t == 0) {
+    int inf = 0;
+    // first failing pivot in elimination order: interiors, then the reduced system
+    for (int k = 0; k <= m && inf == 0; ++k) {
+      const int v = a.info_part[(size_t)e * (m + 1) + k];
+      if (v != 0) inf = (k < m) ? v : lay.p(v - 1) + 1;
+    }
+    s_info = inf;
+  }
+  __syncthreads();
+  const int inf = s_info;
+  double2* scr = a.ws_fin + (size_t)e * 4 * bpbp;
+  double2* G0L = scr;
+  double2* GamL = scr + bpbp;
+  double2* GamR = scr + 2 * bpbp;
+  double2* X1 = scr + 3 * bpbp;
+  double Tval = 0.0;
+  if (a.T) {
+    const double2* CR0 = a.ws_int + (size_t)(e * m) * a.ws_int_chain + (size_t)6 * nmax * bpbp;
+    const double2* GS = a.GS + (size_t)e * 3 * m * bb;
+    const double2* GSrow = a.GSrow + (size_t)e * m * bb;
+    const double2* Z = (m == 1) ? GS + (size_t)m * bb : GSrow + (size_t)(m - 1) * bb;
+    Acc<T, NW> acc;
+    acc_zero<T, NW>(acc);
+    mma<T, NW>(acc, opnd(CR0, BP, BP, BP), opnd(Z, b, b, b), -1.0);
+    store<T, NW>(acc, G0L, BP, BP, BP);
+    const double2* sL = a.sigL + (size_t)e * bb;
+    const double2* sR = a.sigR + (size_t)e * bb;
+    for (int idx = t; idx < BP * BP; idx += NT) {
+      const int r = idx / BP, cc = idx % BP;
+      double2 gl = make_double2(0.0, 0.0), gr = make_double2(0.0, 0.0);
+      if (r < b && cc < b) {
+        const double2 s1 = sL[(size_t)r * b + cc], s2 = sL[(size_t)cc * b + r];
+        gl = make_double2(-(s1.y + s2.y), s1.x - s2.x);
+        const double2 q1 = sR[(size_t)r * b + cc], q2 = sR[(size_t)cc * b + r];
+        gr = make_double2(-(q1.y + q2.y), q1.x - q2.x);
+      }
+      GamL[idx] = gl;
+      GamR[idx] = gr;
+    }
+    __syncthreads();
+    acc_zero<T, NW>(acc);
+    mma<T, NW>(acc, opnd(GamL, BP, BP, BP), opnd(G0L, BP, BP, BP), 1.0);
+    store<T, NW>(acc, X1, BP, BP, BP);
+    __syncthreads();
+    acc_zero<T, NW>(acc);
+    mma<T, NW>(acc, opnd(GamR, BP, BP, BP), opnd(G0L, BP, BP, BP, 1), 1.0);
+    double part = 0.0;
+    const int ln = lane_id();
+    int tr0, tc0;
+    tile_origin<T, NW>(tr0, tc0);
+#pragma unroll
+    for (int r = 0; r < Acc<T, NW>::RR; ++r)
+#pragma unroll
+      for (int c = 0; c < Acc<T, NW>::RC; ++c) {
+        if (tr0 + r >= T || tc0 + c >= T) continue;
+        const int jj = 16 * (tc0 + c) + c_col(ln);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int kk = 16 * (tr0 + r) + c_row(ln, v);
+          const double2 x1 = X1[(size_t)jj * BP + kk];
+          part += acc.re[r][c][v] * x1.x - acc.im[r][c][v] * x1.y;
+        }
+      }
+    Tval = wg_sum<NW>(part, red);
+  }
+  if (inf != 0) {
+    const double qnan = __builtin_nan("");
+    double2* Gout = a.G + (size_t)e * 3 * a.l * bb;
+    for (size_t idx = t; idx < (size_t)3 * a.l * bb; idx += NT) Gout[idx] = make_double2(qnan, qnan);
+    Tval = qnan;
+  }
+  if (t == 0) {
+    if (a.T) a.T[e] = Tval;
+    a.info[e] = inf;
+  }
+}
+
+template <int T>
+static hipError_t launch_dd_T(const DDArgs& a, hipStream_t s) {
+  constexpr int NW = T >= 7 ? 8 : 4;
+  const int chains = a.ne * a.m;
+  hipLaunchKernelGGL((ddrgf_interior_kernel<T, NW>), dim3(chains), dim3(64 * NW), 0, s, a);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL((ddrgf_schur_kernel<T, NW>), dim3(chains), dim3(64 * NW), 0, s, a);
+  if ((err = hipGetLastError()) != hipSuccess) return err;
+  SweepArgs r{};
+  r.H = a.MS;
+  r.h_stride = (size_t)3 * a.m * a.b * a.b;
+  r.direct = 1;
+  r.G = a.GS;
+  r.g_stride = (size_t)3 * a.m * a.b * a.b;
+  r.first_row = a.GSrow;
+  r.T = nullptr;
+  r.info = a.info_part;   // strided below: reduced status goes to slot m of each energy
+  r.ws = a.ws_red;
+  r.ws_chain = a.ws_red_chain;
+  r.l = a.m;
+  r.b = a.b;
+  r.chains = a.ne;
+  r.info_stride = a.m + 1;
+  r.info_offset = a.m;
+  if ((err = launch_rgf_sweep(r, s)) != hipSuccess) return err;
+  hipLaunchKernelGGL((ddrgf_recover_kernel<T, NW>), dim3(chains), dim3(64 * NW), 0, s, a);
+  if ((err = hipGetLastError()) != hipSuccess) return err;
+  hipLaunchKernelGGL((ddrgf_finalize_kernel<T, NW>), dim3(a.ne), dim3(64 * NW), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_ddrgf(const DDArgs& a, hipStream_t s) {
+  switch (padded_block(a.b) / 16) {
+    case 1: return launch_dd_T<1>(a, s);
+    case 2: return launch_dd_T<2>(a, s);
+    case 3: return launch_dd_T<3>(a, s);
+    case 4: return launch_dd_T<4>(a, s);
+    case 5: return launch_dd_T<5>(a, s);
+    case 6: return launch_dd_T<6>(a, s);
+    case 7: return launch_dd_T<7>(a, s);
+    case 8: return launch_dd_T<8>(a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+void ddrgf_layout_host(int l, int m, int* base, int* rem) {
+  DDLayout d = dd_layout(l, m);
+  *base = d.base;
+  *rem = d.rem;
+}
+
+}  // namespace rgfk

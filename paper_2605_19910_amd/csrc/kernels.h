@@ -25,7 +25,8 @@ struct SweepArgs {
   size_t g_stride;           // elements between the outputs of consecutive chains
   double2* first_row;        // optional out [chains][l][b][b]: G_{0,i} (null = not wanted)
   double* T;                 // optional out [chains]
-  int* info;                 // [chains]
+  int* info;                 // status of chain c at info[c * info_stride + info_offset]
+  int info_stride, info_offset;
   double2* ws;               // workspace, ws_chain elements per chain
   size_t ws_chain;
   int l, b, chains;
@@ -34,5 +35,31 @@ struct SweepArgs {
 size_t sweep_ws_chain_elems(int l, int bp);
 int padded_block(int b);
 hipError_t launch_rgf_sweep(const SweepArgs& a, hipStream_t s);
+
+// DDRGF (Algorithm 2), block tridiagonal, one level.
+struct DDArgs {
+  const double2* H;          // band [3][l][b][b], shared by all energies
+  const double2* sigL;       // [ne][b][b]
+  const double2* sigR;
+  const double* E;           // [ne]
+  double eta_d;
+  double2* G;                // out band [ne][3][l][b][b]
+  double* T;                 // out [ne] or null
+  int* info;                 // out [ne]
+  int l, b, m, ne;
+  double2* ws_int;           // per (energy, interior) chain: ws_int_chain elements
+  size_t ws_int_chain;
+  double2* MS;               // reduced band [ne][3][m][b][b]
+  double2* GS;               // its inverse band [ne][3][m][b][b]
+  double2* GSrow;            // first block row of the reduced inverse [ne][m][b][b]
+  double2* ws_red;           // sweep workspace of the reduced system
+  size_t ws_red_chain;
+  int* info_part;            // [ne][m + 1] per-stage status
+  double2* ws_fin;           // [ne][4][bp][bp]
+};
+
+size_t ddrgf_interior_ws_elems(int nmax, int bp);
+void ddrgf_layout_host(int l, int m, int* base, int* rem);
+hipError_t launch_ddrgf(const DDArgs& a, hipStream_t s);
 
 }  // namespace rgfk

@@ -182,7 +182,7 @@ __global__ __launch_bounds__(64 * NW, 1) void rgf_sweep_kernel(SweepArgs a) {
   }
   if (t == 0) {
     if (a.T && !a.direct) a.T[e] = Tval;
-    if (a.info) a.info[e] = bad_layer >= 0 ? bad_layer + 1 : 0;
+    if (a.info) a.info[(size_t)e * a.info_stride + a.info_offset] = bad_layer >= 0 ? bad_layer + 1 : 0;
   }
 }
 
