@@ -139,7 +139,8 @@ def dense_selected(H, w, E, sigma_L, sigma_R, eta_d=0.0, full: bool = False):
 # ----------------------------------------------------------------------------
 
 def rgf(H, E, sigma_L, sigma_R, eta_d=0.0, counter: Optional[OpCounter] = None,
-        extras: bool = True, pivot_cond: bool = False) -> Dict[str, np.ndarray]:
+        extras: bool = True, pivot_cond: bool = False,
+        pivot_noise: Optional[int] = None) -> Dict[str, np.ndarray]:
     """Sequential RGF, w = 1.
 
     Upward pass (eliminate layer l-1 first, then l-2, ... 0): the Schur pivot of the
@@ -149,7 +150,9 @@ def rgf(H, E, sigma_L, sigma_R, eta_d=0.0, counter: Optional[OpCounter] = None,
     Downward pass: G_00 = S_0^{-1}; for i >= 1, G_{i-1,i} = -G_{i-1,i-1} U_i,
     G_{i,i-1} = -L_i G_{i-1,i-1}, G_ii = S_i^{-1} - L_i G_{i-1,i}.
 
-    ``pivot_cond`` also returns max_i kappa_1(S_i) (see :func:`nrgf`).
+    ``pivot_cond`` also returns max_i kappa_1(S_i); ``pivot_noise`` perturbs every
+    Schur pivot by a relative u-sized Gaussian before factorisation (both as in
+    :func:`nrgf`).
 
     With ``extras`` also the first block row/column and last block row/column of
     G = M^{-1}, propagated with the same multipliers (these are the far-corner
@@ -166,12 +169,20 @@ def rgf(H, E, sigma_L, sigma_R, eta_d=0.0, counter: Optional[OpCounter] = None,
     lu = [None] * l
     U = [None] * l       # U[i] = M_{i-1,i} S_i^{-1}
     L = [None] * l       # L[i] = S_i^{-1} M_{i,i-1}
-    lu[l - 1] = ops.lu(M(l - 1, l - 1))
+    nrng = None if pivot_noise is None else np.random.default_rng(pivot_noise)
+
+    def noisy(S):
+        if nrng is None:
+            return S
+        xi = nrng.standard_normal((b, b)) + 1j * nrng.standard_normal((b, b))
+        return S * (1.0 + 2.0 ** -53 * xi)
+
+    lu[l - 1] = ops.lu(noisy(M(l - 1, l - 1)))
     for i in range(l - 2, -1, -1):
         U[i + 1] = ops.solve_right(M(i, i + 1), lu[i + 1])
         L[i + 1] = ops.solve_left(lu[i + 1], M(i + 1, i))
         S = M(i, i) - ops.gemm(M(i, i + 1), L[i + 1])
-        lu[i] = ops.lu(S)
+        lu[i] = ops.lu(noisy(S))
 
     eye = np.eye(b, dtype=np.complex128)
     G = np.zeros((3, l, b, b), dtype=np.complex128)
@@ -213,7 +224,7 @@ def rgf(H, E, sigma_L, sigma_R, eta_d=0.0, counter: Optional[OpCounter] = None,
 
 def nrgf(Mb: Callable[[int, int], Optional[np.ndarray]], l: int, b: int, w: int,
          counter: Optional[OpCounter] = None, halo: int = 0,
-         pivot_cond: bool = False) -> Dict[str, np.ndarray]:
+         pivot_cond: bool = False, pivot_noise: Optional[int] = None) -> Dict[str, np.ndarray]:
     """Native n-diagonal RGF (n = 2w + 1) on the blocks returned by ``Mb``.
 
     Upward pass (Proposition 3): eliminate layers l-1, ..., 0.  When layer i is
@@ -233,6 +244,11 @@ def nrgf(Mb: Callable[[int, int], Optional[np.ndarray]], l: int, b: int, w: int,
     ``pivot_cond`` also returns max_i kappa_1(S_ii), the condition number of the
     worst Schur pivot: the block elimination does not pivot across blocks, so
     rounding errors are amplified by it (not by kappa(M)).
+
+    ``pivot_noise`` (a seed) multiplies every entry of every Schur pivot by
+    (1 + u xi), xi ~ N(0, 1), u = 2^-53, before it is factorised: a second run
+    of the same algorithm with independent rounding-sized perturbations, whose
+    distance to the unperturbed run estimates the algorithm's rounding error.
 
     ``halo`` > 0 additionally returns the first/last ``halo`` block rows and
     columns of M^{-1} (the "internal halos" that DDRGF needs from each interior):
@@ -254,7 +270,11 @@ def nrgf(Mb: Callable[[int, int], Optional[np.ndarray]], l: int, b: int, w: int,
     lu = [None] * l
     U: Dict[tuple, np.ndarray] = {}
     L: Dict[tuple, np.ndarray] = {}
+    nrng = None if pivot_noise is None else np.random.default_rng(pivot_noise)
     for i in range(l - 1, -1, -1):
+        if nrng is not None:
+            xi = nrng.standard_normal((b, b)) + 1j * nrng.standard_normal((b, b))
+            S[(i, i)] = S[(i, i)] * (1.0 + 2.0 ** -53 * xi)
         lu[i] = ops.lu(S[(i, i)])
         C = range(max(0, i - w), i)
         for c in C:

@@ -448,4 +448,51 @@ __device__ __forceinline__ double wg_sum(double v, double* red /* LDS, >= NW */)
   return s;
 }
 
+// T = Re Tr[Gamma_L R Gamma_R R^H] with Gamma = i (Sigma - Sigma^H), R = G_{0,l-1}
+// (padded bp x bp, ld = bp, in global memory).  GamL, GamR, X1: bp x bp scratch.
+// All threads call it; the result is returned to every thread.
+template <int T, int NW>
+__device__ double transmission(Acc<T, NW>& acc, const double2* R, const double2* sL, const double2* sR,
+                               int b, double2* GamL, double2* GamR, double2* X1, double* red) {
+  constexpr int BP = 16 * T;
+  constexpr int NT = 64 * NW;
+  for (int idx = threadIdx.x; idx < BP * BP; idx += NT) {
+    const int r = idx / BP, c = idx % BP;
+    double2 gl = make_double2(0.0, 0.0), gr = make_double2(0.0, 0.0);
+    if (r < b && c < b) {
+      const double2 s1 = sL[(size_t)r * b + c], s2 = sL[(size_t)c * b + r];
+      gl = make_double2(-(s1.y + s2.y), s1.x - s2.x);
+      const double2 q1 = sR[(size_t)r * b + c], q2 = sR[(size_t)c * b + r];
+      gr = make_double2(-(q1.y + q2.y), q1.x - q2.x);
+    }
+    GamL[idx] = gl;
+    GamR[idx] = gr;
+  }
+  __syncthreads();
+  acc_zero<T, NW>(acc);
+  mma<T, NW>(acc, opnd(GamL, BP, BP, BP), opnd(R, BP, BP, BP), 1.0);
+  store<T, NW>(acc, X1, BP, BP, BP);
+  __syncthreads();
+  acc_zero<T, NW>(acc);
+  mma<T, NW>(acc, opnd(GamR, BP, BP, BP), opnd(R, BP, BP, BP, 1), 1.0);
+  double part = 0.0;
+  const int ln = lane_id();
+  int tr0, tc0;
+  tile_origin<T, NW>(tr0, tc0);
+#pragma unroll
+  for (int r = 0; r < Acc<T, NW>::RR; ++r)
+#pragma unroll
+    for (int c = 0; c < Acc<T, NW>::RC; ++c) {
+      if (tr0 + r >= T || tc0 + c >= T) continue;
+      const int jj = 16 * (tc0 + c) + c_col(ln);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int kk = 16 * (tr0 + r) + c_row(ln, v);
+        const double2 x1 = X1[(size_t)jj * BP + kk];
+        part += acc.re[r][c][v] * x1.x - acc.im[r][c][v] * x1.y;
+      }
+    }
+  return wg_sum<NW>(part, red);
+}
+
 }  // namespace rgfk

@@ -351,45 +351,9 @@ __global__ __launch_bounds__(64 * NW, 1) void ddrgf_finalize_kernel(DDArgs a) {
     acc_zero<T, NW>(acc);
     mma<T, NW>(acc, opnd(CR0, BP, BP, BP), opnd(Z, b, b, b), -1.0);
     store<T, NW>(acc, G0L, BP, BP, BP);
-    const double2* sL = a.sigL + (size_t)e * bb;
-    const double2* sR = a.sigR + (size_t)e * bb;
-    for (int idx = t; idx < BP * BP; idx += NT) {
-      const int r = idx / BP, cc = idx % BP;
-      double2 gl = make_double2(0.0, 0.0), gr = make_double2(0.0, 0.0);
-      if (r < b && cc < b) {
-        const double2 s1 = sL[(size_t)r * b + cc], s2 = sL[(size_t)cc * b + r];
-        gl = make_double2(-(s1.y + s2.y), s1.x - s2.x);
-        const double2 q1 = sR[(size_t)r * b + cc], q2 = sR[(size_t)cc * b + r];
-        gr = make_double2(-(q1.y + q2.y), q1.x - q2.x);
-      }
-      GamL[idx] = gl;
-      GamR[idx] = gr;
-    }
     __syncthreads();
-    acc_zero<T, NW>(acc);
-    mma<T, NW>(acc, opnd(GamL, BP, BP, BP), opnd(G0L, BP, BP, BP), 1.0);
-    store<T, NW>(acc, X1, BP, BP, BP);
-    __syncthreads();
-    acc_zero<T, NW>(acc);
-    mma<T, NW>(acc, opnd(GamR, BP, BP, BP), opnd(G0L, BP, BP, BP, 1), 1.0);
-    double part = 0.0;
-    const int ln = lane_id();
-    int tr0, tc0;
-    tile_origin<T, NW>(tr0, tc0);
-#pragma unroll
-    for (int r = 0; r < Acc<T, NW>::RR; ++r)
-#pragma unroll
-      for (int c = 0; c < Acc<T, NW>::RC; ++c) {
-        if (tr0 + r >= T || tc0 + c >= T) continue;
-        const int jj = 16 * (tc0 + c) + c_col(ln);
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int kk = 16 * (tr0 + r) + c_row(ln, v);
-          const double2 x1 = X1[(size_t)jj * BP + kk];
-          part += acc.re[r][c][v] * x1.x - acc.im[r][c][v] * x1.y;
-        }
-      }
-    Tval = wg_sum<NW>(part, red);
+    Tval = transmission<T, NW>(acc, G0L, a.sigL + (size_t)e * bb, a.sigR + (size_t)e * bb, b, GamL, GamR,
+                               X1, red);
   }
   if (inf != 0) {
     const double qnan = __builtin_nan("");

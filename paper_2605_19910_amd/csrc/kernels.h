@@ -62,4 +62,40 @@ size_t ddrgf_interior_ws_elems(int nmax, int bp);
 void ddrgf_layout_host(int l, int m, int* base, int* rem);
 hipError_t launch_ddrgf(const DDArgs& a, hipStream_t s);
 
+// Native n-diagonal sweep (w >= 1), one workgroup per energy.
+struct NSweepArgs {
+  const double2* H;          // band [2w+1][l][b][b]
+  const double2* sigL;       // [ne][b][b]
+  const double2* sigR;
+  const double* E;
+  double eta_d;
+  double2* G;                // out band [ne][2w+1][l][b][b]
+  double* T;                 // out [ne] or null
+  int* info;                 // out [ne]
+  double2* ws;
+  size_t ws_chain;
+  int l, b, w, ne;
+};
+
+size_t nrgf_ws_chain_elems(int l, int w, int bp);
+hipError_t launch_nrgf_sweep(const NSweepArgs& a, hipStream_t s);
+
+// Super-block view (w layers -> one layer of w*b orbitals) of a band and its leads.
+struct FuseArgs {
+  const double2* H;          // [2w+1][l][b][b]
+  const double2* sigL;       // [ne][b][b]
+  const double2* sigR;
+  double2* Hf;               // [3][l/w][wb][wb]
+  double2* sigLf;            // [ne][wb][wb]
+  double2* sigRf;
+  const double2* Gf;         // [ne][3][l/w][wb][wb]
+  double2* G;                // [ne][2w+1][l][b][b]
+  const int* info_f;         // [ne] status in super-layers
+  int* info;                 // [ne] status in layers
+  int l, b, w, ne;
+};
+
+hipError_t launch_fuse(const FuseArgs& a, hipStream_t s);
+hipError_t launch_unfuse(const FuseArgs& a, hipStream_t s);
+
 }  // namespace rgfk

@@ -128,48 +128,8 @@ __global__ __launch_bounds__(64 * NW, 1) void rgf_sweep_kernel(SweepArgs a) {
 
   // ---------------- transmission ----------------
   double Tval = 0.0;
-  if (a.T && !a.direct) {
-    for (int idx = t; idx < BP * BP; idx += NT) {
-      const int r = idx / BP, c = idx % BP;
-      double2 gl = make_double2(0.0, 0.0), gr = make_double2(0.0, 0.0);
-      if (r < b && c < b) {
-        const double2 s1 = sL[(size_t)r * b + c], s2 = sL[(size_t)c * b + r];
-        gl = make_double2(-(s1.y + s2.y), s1.x - s2.x);
-        const double2 q1 = sR[(size_t)r * b + c], q2 = sR[(size_t)c * b + r];
-        gr = make_double2(-(q1.y + q2.y), q1.x - q2.x);
-      }
-      GamL[idx] = gl;
-      GamR[idx] = gr;
-    }
-    __syncthreads();
-    const double2* Rl = Rb + (size_t)((l - 1) & 1) * bpbp;
-    acc_zero<T, NW>(acc);
-    mma<T, NW>(acc, opnd(GamL, BP, BP, BP), opnd(Rl, BP, BP, BP), 1.0);
-    store<T, NW>(acc, X1, BP, BP, BP);
-    __syncthreads();
-    acc_zero<T, NW>(acc);
-    mma<T, NW>(acc, opnd(GamR, BP, BP, BP), opnd(Rl, BP, BP, BP, 1), 1.0);
-    double part = 0.0;
-    {
-      const int ln = lane_id();
-      int tr0, tc0;
-      tile_origin<T, NW>(tr0, tc0);
-#pragma unroll
-      for (int r = 0; r < Acc<T, NW>::RR; ++r)
-#pragma unroll
-        for (int c = 0; c < Acc<T, NW>::RC; ++c) {
-          if (tr0 + r >= T || tc0 + c >= T) continue;
-          const int jj = 16 * (tc0 + c) + c_col(ln);
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int kk = 16 * (tr0 + r) + c_row(ln, v);
-            const double2 x1 = X1[(size_t)jj * BP + kk];
-            part += acc.re[r][c][v] * x1.x - acc.im[r][c][v] * x1.y;
-          }
-        }
-    }
-    Tval = wg_sum<NW>(part, red);
-  }
+  if (a.T && !a.direct)
+    Tval = transmission<T, NW>(acc, Rb + (size_t)((l - 1) & 1) * bpbp, sL, sR, b, GamL, GamR, X1, red);
 
   // ---------------- status ----------------
   if (bad_layer >= 0) {

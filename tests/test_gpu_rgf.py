@@ -3,8 +3,9 @@
 Tolerances (FP64 path): relative Frobenius error over all selected blocks of one
 energy <= 1e-10, and |T_gpu - T_oracle| <= 1e-10 * max(1, T).  Both sides run the
 same block elimination (no pivoting across blocks), so their difference is rounding
-amplified by the Schur pivots' conditioning kappa; at the full 256 x 128 size kappa
-reaches ~1e6-1e7 for this generator and the bound there is max(1e-10, 2 kappa u).
+amplified by the Schur pivots' conditioning; at the full 256 x 128 size the pivots'
+condition numbers reach ~1e6-1e7 for this generator and the bound there is
+max(1e-10, 2 e_noise), e_noise = the oracle's own rounding spread (see check_energies).
 """
 import numpy as np
 import pytest
@@ -49,21 +50,24 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-U64 = 2.0 ** -53
-
-
 def check_energies(wl, G, T, info, energies, eta_d=None, conditioned=False):
-    """Compare with the oracle.  ``conditioned``: the bound is max(1e-10, 2 kappa u),
-    kappa = worst Schur-pivot condition number of the energy (from the oracle), the
-    rounding amplification of a block elimination without pivoting across blocks."""
+    """Compare with the oracle.  ``conditioned``: the bound is max(1e-10, 2 e_noise),
+    where e_noise is the distance between the oracle and a second oracle run whose
+    Schur pivots carry independent u-sized perturbations: the rounding spread of
+    the block elimination itself (no pivoting across blocks) at this energy."""
     eta_d = wl.eta_d if eta_d is None else eta_d
     assert np.all(info == 0), info
     for e in energies:
-        r = oracle.rgf(wl.H, wl.energies[e], wl.sigma_L[e], wl.sigma_R[e], eta_d, extras=True,
-                       pivot_cond=conditioned)
+        args = (wl.H, wl.energies[e], wl.sigma_L[e], wl.sigma_R[e], eta_d)
+        r = oracle.rgf(*args, extras=True)
         ref = r["G"]
         Tref = oracle.transmission(r["row0"][wl.l - 1], wl.sigma_L[e], wl.sigma_R[e])
-        tol = max(TOL, 2.0 * r["pivot_cond"] * U64) if conditioned else TOL
+        tol = TOL
+        if conditioned:
+            rn = oracle.rgf(*args, extras=True, pivot_noise=1000 + e)
+            Tn = oracle.transmission(rn["row0"][wl.l - 1], wl.sigma_L[e], wl.sigma_R[e])
+            e_noise = max(rel(rn["G"], ref), abs(Tn - Tref) / max(1.0, abs(Tref)))
+            tol = max(TOL, 2.0 * e_noise)
         err = rel(mask_band(G[e], wl.w), ref)
         assert err <= tol, (e, err, tol)
         assert abs(T[e] - Tref) <= tol * max(1.0, abs(Tref)), (e, T[e], Tref, tol)

@@ -434,3 +434,19 @@ def test_gradient_finite_difference_and_dense():
             Tp = O.solve_energy(Hp, 1, E, sL, sR)[1]
             Tm = O.solve_energy(Hm, 1, E, sL, sR)[1]
             assert abs((Tp - Tm) / (2 * h) - g[i, s]) < 1e-7
+
+
+def test_pivot_noise_estimator_is_rounding_sized():
+    """The u-perturbed second run used as a rounding-spread yardstick differs from the
+    clean run by a rounding-sized amount on a well-conditioned system, and is a
+    different computation (not bitwise equal)."""
+    wl = make_random(12, 8, 1, 1, seed=21, eta=1e-3)
+    args = (wl.H, wl.energies[0], wl.sigma_L[0], wl.sigma_R[0], 0.1)
+    r = O.rgf(*args, extras=False)
+    rn = O.rgf(*args, extras=False, pivot_noise=3)
+    d = rel(rn["G"], r["G"])
+    assert 0 < d < 1e-13
+    Mb = O.block_accessor(wl.H, 1, *args[1:])
+    r2 = O.nrgf(Mb, 12, 8, 1)
+    rn2 = O.nrgf(Mb, 12, 8, 1, pivot_noise=3)
+    assert 0 < rel(rn2["G"], r2["G"]) < 1e-13
