@@ -111,7 +111,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--method", default="both", choices=["rgf", "ddrgf", "both"])
+    ap.add_argument("--method", default="both", choices=["rgf", "ddrgf", "mixed", "both"])
     ap.add_argument("--domains", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-workers", type=int, default=0)
@@ -151,27 +151,28 @@ def main():
     info = torch.empty((ne,), dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream(dev)
 
-    def run_leg(method: str):
+    def run_leg(leg: str):
+        method, prec = leg.split("_")
         if method == "rgf":
-            plan = binding.Plan(l, b, w, ne, method="rgf")
+            plan = binding.Plan(l, b, w, ne, method="rgf", precision=prec)
             fn = binding.rgf_solve
         else:
-            plan = binding.Plan(l, b, w, ne, method="ddrgf", domains=args.domains)
+            plan = binding.Plan(l, b, w, ne, method="ddrgf", domains=args.domains, precision=prec)
             fn = binding.ddrgf_solve
         ws = torch.empty((plan.workspace_bytes,), dtype=torch.uint8, device=dev)
 
         def step():
             fn(plan, H, sL, sR, E, wl.eta_d, G, T, info, ws, stream.cuda_stream)
 
-        log(f"{method}: inputs on the GPU; warmup")
+        log(f"{leg}: inputs on the GPU; warmup")
         for _ in range(args.warmup):
             step()
         torch.cuda.synchronize()
         if not bool((info == 0).all()) or not bool(torch.isfinite(T).all()):
-            print(json.dumps({"error": f"{method} solve reported a failure",
+            print(json.dumps({"error": f"{leg} solve reported a failure",
                               "info": info.cpu().tolist()}), flush=True)
             sys.exit(1)
-        log(f"{method}: warmup done; timing")
+        log(f"{leg}: warmup done; timing")
         events = []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -188,7 +189,7 @@ def main():
         res = {"value": ne * args.steps / wall, "ms_per_step": 1000.0 * wall / args.steps,
                "gpu_ms_per_step": step_ms}
         # dominant kernel, timed alone with HIP events on the same stream
-        if method == "rgf":
+        if leg == "rgf_fp64":
             res["kernel"] = f"rgf_sweep_kernel (b={b}, l={l}, {ne} chains)"
             res["kernel_ms"] = step_ms
             res["flops_per_launch"] = rgf_flops_per_energy(l, b) * ne
@@ -198,14 +199,35 @@ def main():
             res["kernel_ms"] = None   # filled from the per-kernel profile when available
         del ws, plan
         torch.cuda.empty_cache()
-        log(f"{method}: {res['value']:.2f} energy points/s, {step_ms:.2f} ms per step")
+        if prec != "fp64" and ref_G is not None:
+            res["err_vs_fp64"] = rel_err_stats(G, T, ref_G, ref_T)
+        log(f"{leg}: {res['value']:.2f} energy points/s, {step_ms:.2f} ms per step")
         return res
 
+    def rel_err_stats(Gx, Tx, Gr, Tr):
+        # per-energy relative Frobenius error of every band block inside the matrix, and of T
+        errs = []
+        for e in range(ne):
+            d = torch.linalg.vector_norm((Gx[e] - Gr[e])[band_mask]).item()
+            n = torch.linalg.vector_norm(Gr[e][band_mask]).item()
+            errs.append(d / n)
+        terr = ((Tx - Tr).abs() / torch.clamp(Tr.abs(), min=1.0)).cpu().numpy()
+        return {"G_rel_max": float(np.max(errs)), "G_rel_median": float(np.median(errs)),
+                "T_rel_max": float(np.max(terr)), "T_rel_median": float(np.median(terr))}
+
+    band_mask = torch.ones((2 * w + 1, l, b, b), dtype=torch.bool, device=dev)
+    band_mask[0, 0] = False
+    band_mask[2 * w, l - 1] = False
+    ref_G = ref_T = None
+    names = {"rgf": ["rgf_fp64"], "ddrgf": ["ddrgf_fp64"], "mixed": ["rgf_fp64", "rgf_fp32"],
+             "both": ["rgf_fp64", "ddrgf_fp64", "rgf_fp32"]}[args.method]
     legs = {}
-    for method in (["rgf", "ddrgf"] if args.method == "both" else [args.method]):
-        legs[method] = run_leg(method)
+    for leg in names:
+        legs[leg] = run_leg(leg)
+        if leg == "rgf_fp64":
+            ref_G, ref_T = G.clone(), T.clone()
     best = max(legs, key=lambda k: legs[k]["value"])
-    lead = legs["rgf"] if "rgf" in legs else legs[best]
+    lead = legs["rgf_fp64"] if "rgf_fp64" in legs else legs[best]
     value = legs[best]["value"]
     ms_per_step = legs[best]["ms_per_step"]
     kern_ms = lead["kernel_ms"]
@@ -227,13 +249,14 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c128 (f64)",
+        "dtype": "c128 (f64)" if best.endswith("fp64") else "c128 storage, f32 products / f64 pivots",
         "data": "synthetic: seeded random Hermitian block band, closed-form lead self-energies",
         "config": {"workload": "block-tridiagonal, l=256 layers, b=128, 64 energies in [-2,2], "
                                "eta=1e-6, seed 102",
                    "method": {"rgf": "sequential RGF (Algorithm 1)",
-                              "ddrgf": f"DDRGF (Algorithm 2), {args.domains} domains"}[best],
-                   "precision": "fp64",
+                              "ddrgf": f"DDRGF (Algorithm 2), {args.domains} domains"}[best.split("_")[0]],
+                   "precision": {"fp64": "fp64", "fp32": "mixed: FP32-MFMA products, FP64 pivots + refinement"}[
+                       best.split("_")[1]],
                    "parallelism": "one workgroup per energy (RGF) / per (energy, domain) (DDRGF)"},
         "roofline": roofline,
         "legs": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}

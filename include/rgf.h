@@ -59,8 +59,13 @@ typedef enum {
 
 typedef enum {
   RGF_FP64 = 0,          /* every product and pivot in FP64 */
-  RGF_MIXED_FP32 = 1,    /* reserved: FP32 products, FP64 pivots */
-  RGF_MIXED_BF16X3 = 2   /* reserved: split-BF16 products, FP64 pivots */
+  RGF_MIXED_FP32 = 1,    /* every block product on FP32 MFMA (operands rounded to FP32,
+                            FP32 accumulation, widened to FP64), Schur pivots inverted in
+                            FP64 and refined once in FP64: g <- g + g (I - S g).
+                            Sequential method with w = 1 only (else RGF_ERR_UNSUPPORTED):
+                            on DDRGF's closed interiors FP32 products lose all accuracy.
+                            The error grows with the Schur pivots' conditioning. */
+  RGF_MIXED_BF16X3 = 2   /* reserved, not supported: split-BF16 products */
 } rgf_precision_t;
 
 typedef enum {

@@ -16,6 +16,7 @@ from .rgf_oracle import (  # noqa: F401
     gamma_of,
     nrgf,
     rgf,
+    rgf_mixed_products,
     solve_energy,
     transmission,
     transmission_g11,

@@ -140,7 +140,7 @@ def dense_selected(H, w, E, sigma_L, sigma_R, eta_d=0.0, full: bool = False):
 
 def rgf(H, E, sigma_L, sigma_R, eta_d=0.0, counter: Optional[OpCounter] = None,
         extras: bool = True, pivot_cond: bool = False,
-        pivot_noise: Optional[int] = None) -> Dict[str, np.ndarray]:
+        pivot_noise: Optional[int] = None, noise_scale: float = 2.0 ** -53) -> Dict[str, np.ndarray]:
     """Sequential RGF, w = 1.
 
     Upward pass (eliminate layer l-1 first, then l-2, ... 0): the Schur pivot of the
@@ -151,8 +151,8 @@ def rgf(H, E, sigma_L, sigma_R, eta_d=0.0, counter: Optional[OpCounter] = None,
     G_{i,i-1} = -L_i G_{i-1,i-1}, G_ii = S_i^{-1} - L_i G_{i-1,i}.
 
     ``pivot_cond`` also returns max_i kappa_1(S_i); ``pivot_noise`` perturbs every
-    Schur pivot by a relative u-sized Gaussian before factorisation (both as in
-    :func:`nrgf`).
+    Schur pivot by a relative Gaussian of size ``noise_scale`` (default u) before
+    factorisation (both as in :func:`nrgf`).
 
     With ``extras`` also the first block row/column and last block row/column of
     G = M^{-1}, propagated with the same multipliers (these are the far-corner
@@ -175,7 +175,7 @@ def rgf(H, E, sigma_L, sigma_R, eta_d=0.0, counter: Optional[OpCounter] = None,
         if nrng is None:
             return S
         xi = nrng.standard_normal((b, b)) + 1j * nrng.standard_normal((b, b))
-        return S * (1.0 + 2.0 ** -53 * xi)
+        return S * (1.0 + noise_scale * xi)
 
     lu[l - 1] = ops.lu(noisy(M(l - 1, l - 1)))
     for i in range(l - 2, -1, -1):
@@ -218,13 +218,53 @@ def rgf(H, E, sigma_L, sigma_R, eta_d=0.0, counter: Optional[OpCounter] = None,
     return out
 
 
+def rgf_mixed_products(H, E, sigma_L, sigma_R, eta_d=0.0) -> Dict[str, np.ndarray]:
+    """Algorithm 1 with every block product rounded to FP32 (operands rounded to
+    complex64, product accumulated in single precision by NumPy/BLAS cgemm, result
+    widened to complex128), while each Schur pivot is inverted in FP64 and refined
+    once in FP64, g <- g + g (I - S g).  This is the definition of the mixed
+    precision variant (the paper has none; its code is only type-generic, Sec. 4),
+    written out so the GPU's mixed path can be compared with the same arithmetic.
+    Returns the band and the first block row's last block (for T)."""
+    l, b = H.shape[1], H.shape[2]
+    M = block_accessor(H, 1, E, sigma_L, sigma_R, eta_d)
+    eye = np.eye(b, dtype=np.complex128)
+
+    def p32(A, B):
+        return (A.astype(np.complex64) @ B.astype(np.complex64)).astype(np.complex128)
+
+    g = [None] * l
+    U = [None] * l
+    L = [None] * l
+    S = M(l - 1, l - 1)
+    for i in range(l - 1, -1, -1):
+        gi = np.linalg.inv(S)
+        gi = gi + gi @ (eye - S @ gi)
+        g[i] = gi
+        if i == 0:
+            break
+        L[i] = p32(gi, M(i, i - 1))
+        U[i] = p32(M(i - 1, i), gi)
+        S = M(i - 1, i - 1) - p32(M(i - 1, i), L[i])
+    G = np.zeros((3, l, b, b), dtype=np.complex128)
+    G[1, 0] = g[0]
+    R = g[0]
+    for i in range(1, l):
+        G[2, i - 1] = -p32(G[1, i - 1], U[i])
+        G[0, i] = -p32(L[i], G[1, i - 1])
+        R = -p32(R, U[i])
+        G[1, i] = g[i] - p32(L[i], G[2, i - 1])
+    return {"G": G, "G_0_last": R}
+
+
 # ----------------------------------------------------------------------------
 # RGF for block n-diagonal systems (Sec. 2.3)
 # ----------------------------------------------------------------------------
 
 def nrgf(Mb: Callable[[int, int], Optional[np.ndarray]], l: int, b: int, w: int,
          counter: Optional[OpCounter] = None, halo: int = 0,
-         pivot_cond: bool = False, pivot_noise: Optional[int] = None) -> Dict[str, np.ndarray]:
+         pivot_cond: bool = False, pivot_noise: Optional[int] = None,
+         noise_scale: float = 2.0 ** -53) -> Dict[str, np.ndarray]:
     """Native n-diagonal RGF (n = 2w + 1) on the blocks returned by ``Mb``.
 
     Upward pass (Proposition 3): eliminate layers l-1, ..., 0.  When layer i is
@@ -246,9 +286,10 @@ def nrgf(Mb: Callable[[int, int], Optional[np.ndarray]], l: int, b: int, w: int,
     rounding errors are amplified by it (not by kappa(M)).
 
     ``pivot_noise`` (a seed) multiplies every entry of every Schur pivot by
-    (1 + u xi), xi ~ N(0, 1), u = 2^-53, before it is factorised: a second run
-    of the same algorithm with independent rounding-sized perturbations, whose
-    distance to the unperturbed run estimates the algorithm's rounding error.
+    (1 + s xi), xi ~ N(0, 1), s = ``noise_scale`` (default u = 2^-53), before it
+    is factorised: a second run of the same algorithm with independent
+    rounding-sized perturbations, whose distance to the unperturbed run estimates
+    the algorithm's rounding error at that precision (s = 2^-24 for FP32 products).
 
     ``halo`` > 0 additionally returns the first/last ``halo`` block rows and
     columns of M^{-1} (the "internal halos" that DDRGF needs from each interior):
@@ -274,7 +315,7 @@ def nrgf(Mb: Callable[[int, int], Optional[np.ndarray]], l: int, b: int, w: int,
     for i in range(l - 1, -1, -1):
         if nrng is not None:
             xi = nrng.standard_normal((b, b)) + 1j * nrng.standard_normal((b, b))
-            S[(i, i)] = S[(i, i)] * (1.0 + 2.0 ** -53 * xi)
+            S[(i, i)] = S[(i, i)] * (1.0 + noise_scale * xi)
         lu[i] = ops.lu(S[(i, i)])
         C = range(max(0, i - w), i)
         for c in C:

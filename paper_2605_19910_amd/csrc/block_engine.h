@@ -209,7 +209,7 @@ __device__ __forceinline__ void load(Acc<T, NW>& acc, const Opnd& X, double sgn 
 // identity on the padding: a diagonal block of M(E) = (E + i eta) I - H - Sigma.
 template <int T, int NW>
 __device__ __forceinline__ void assemble_diag(Acc<T, NW>& acc, const double2* Hd, int b, double2 z,
-                                              const double2* sL, const double2* sR) {
+                                              const double2* sL, const double2* sR, bool add = false) {
   constexpr int RR = Acc<T, NW>::RR;
   constexpr int RC = Acc<T, NW>::RC;
   const int l = lane_id();
@@ -236,9 +236,152 @@ __device__ __forceinline__ void assemble_diag(Acc<T, NW>& acc, const double2* Hd
             x.x = 1.0;
           }
         }
-        acc.re[r][c][v] = x.x;
-        acc.im[r][c][v] = x.y;
+        if (add) {
+          acc.re[r][c][v] += x.x;
+          acc.im[r][c][v] += x.y;
+        } else {
+          acc.re[r][c][v] = x.x;
+          acc.im[r][c][v] = x.y;
+        }
       }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Mixed precision products: operands rounded to FP32 (round to nearest even),
+// v_mfma_f32_16x16x4f32 with FP32 accumulation over the whole k range, the
+// result widened to FP64 once.  F32_ROW(r) maps the row of an FP32 accumulator
+// element onto the FP64 accumulator row of the same lane/element, by feeding the
+// A operand with permuted rows.
+// ---------------------------------------------------------------------------
+typedef float flt4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ flt4 mfma32(float a, float b, flt4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// FP32 16x16x4 accumulator: lane l, element v holds row 4*(l/16) + v (FP64: l/16 + 4v).
+// Feeding A'[r] = A[perm(r)] with perm(4q + v) = q + 4v puts row q + 4v there.
+__device__ __forceinline__ int f32_row(int r) { return (r >> 2) + 4 * (r & 3); }
+
+// acc = sgn * A * B with FP32 products and FP32 accumulation.
+template <int T, int NW>
+__device__ __forceinline__ void gemm_f32(Acc<T, NW>& acc, const Opnd& A, const Opnd& B, double sgn) {
+  constexpr int RR = Acc<T, NW>::RR;
+  constexpr int RC = Acc<T, NW>::RC;
+  constexpr int BP = 16 * T;
+  constexpr int NKS = BP / 4;
+  const int l = lane_id();
+  int tr0, tc0;
+  tile_origin<T, NW>(tr0, tc0);
+  const int li = f32_row(l & 15), lj = l & 15, lk = l >> 4;
+  flt4 cre[RR][RC], cim[RR][RC];
+#pragma unroll
+  for (int r = 0; r < RR; ++r)
+#pragma unroll
+    for (int c = 0; c < RC; ++c) {
+      cre[r][c] = flt4{0.f, 0.f, 0.f, 0.f};
+      cim[r][c] = flt4{0.f, 0.f, 0.f, 0.f};
+    }
+  float2 a[RR], b[RC], an[RR], bn[RC];
+  auto ldA = [&](int r, int k) {
+    const double2 x = opnd_get(A, 16 * (tr0 + r) + li, k);
+    return make_float2((float)x.x, (float)x.y);
+  };
+  auto ldB = [&](int c, int k) {
+    const double2 x = opnd_get(B, k, 16 * (tc0 + c) + lj);
+    return make_float2((float)(sgn * x.x), (float)(sgn * x.y));
+  };
+#pragma unroll
+  for (int r = 0; r < RR; ++r) a[r] = ldA(r, lk);
+#pragma unroll
+  for (int c = 0; c < RC; ++c) b[c] = ldB(c, lk);
+  for (int ks = 0; ks < NKS; ++ks) {
+    if (ks + 1 < NKS) {
+      const int k = 4 * (ks + 1) + lk;
+#pragma unroll
+      for (int r = 0; r < RR; ++r) an[r] = ldA(r, k);
+#pragma unroll
+      for (int c = 0; c < RC; ++c) bn[c] = ldB(c, k);
+    }
+#pragma unroll
+    for (int r = 0; r < RR; ++r) {
+      if (tr0 + r >= T) continue;
+#pragma unroll
+      for (int c = 0; c < RC; ++c) {
+        if (tc0 + c >= T) continue;
+        cre[r][c] = mfma32(a[r].x, b[c].x, cre[r][c]);
+        cre[r][c] = mfma32(-a[r].y, b[c].y, cre[r][c]);
+        cim[r][c] = mfma32(a[r].x, b[c].y, cim[r][c]);
+        cim[r][c] = mfma32(a[r].y, b[c].x, cim[r][c]);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < RR; ++r) a[r] = an[r];
+#pragma unroll
+    for (int c = 0; c < RC; ++c) b[c] = bn[c];
+  }
+#pragma unroll
+  for (int r = 0; r < RR; ++r)
+#pragma unroll
+    for (int c = 0; c < RC; ++c)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        acc.re[r][c][v] = (double)cre[r][c][v];
+        acc.im[r][c][v] = (double)cim[r][c][v];
+      }
+}
+
+// acc = sgn * A * B in the precision selected by MIXED (0: FP64 MFMA, 1: FP32 MFMA).
+template <int MIXED, int T, int NW>
+__device__ __forceinline__ void gemm_to(Acc<T, NW>& acc, const Opnd& A, const Opnd& B, double sgn) {
+  if constexpr (MIXED) {
+    gemm_f32<T, NW>(acc, A, B, sgn);
+  } else {
+    acc_zero<T, NW>(acc);
+    mma<T, NW>(acc, A, B, sgn);
+  }
+}
+
+// acc += sgn * X (X read through an operand view).
+template <int T, int NW>
+__device__ __forceinline__ void add_from(Acc<T, NW>& acc, const Opnd& X, double sgn = 1.0) {
+  constexpr int RR = Acc<T, NW>::RR;
+  constexpr int RC = Acc<T, NW>::RC;
+  const int l = lane_id();
+  int tr0, tc0;
+  tile_origin<T, NW>(tr0, tc0);
+#pragma unroll
+  for (int r = 0; r < RR; ++r)
+#pragma unroll
+    for (int c = 0; c < RC; ++c) {
+      if (tr0 + r >= T || tc0 + c >= T) continue;
+      const int j = 16 * (tc0 + c) + c_col(l);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const double2 x = opnd_get(X, 16 * (tr0 + r) + c_row(l, v), j);
+        acc.re[r][c][v] += sgn * x.x;
+        acc.im[r][c][v] += sgn * x.y;
+      }
+    }
+}
+
+// acc += I on the diagonal.
+template <int T, int NW>
+__device__ __forceinline__ void add_identity(Acc<T, NW>& acc) {
+  constexpr int RR = Acc<T, NW>::RR;
+  constexpr int RC = Acc<T, NW>::RC;
+  const int l = lane_id();
+  int tr0, tc0;
+  tile_origin<T, NW>(tr0, tc0);
+#pragma unroll
+  for (int r = 0; r < RR; ++r)
+#pragma unroll
+    for (int c = 0; c < RC; ++c) {
+      if (tr0 + r >= T || tc0 + c >= T) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        if (16 * (tr0 + r) + c_row(l, v) == 16 * (tc0 + c) + c_col(l)) acc.re[r][c][v] += 1.0;
     }
 }
 
@@ -452,7 +595,7 @@ __device__ __forceinline__ double wg_sum(double v, double* red /* LDS, >= NW */)
 // (padded bp x bp, ld = bp, in global memory).  GamL, GamR, X1: bp x bp scratch.
 // All threads call it; the result is returned to every thread.
 template <int T, int NW>
-__device__ double transmission(Acc<T, NW>& acc, const double2* R, const double2* sL, const double2* sR,
+__device__ __forceinline__ double transmission(Acc<T, NW>& acc, const double2* R, const double2* sL, const double2* sR,
                                int b, double2* GamL, double2* GamR, double2* X1, double* red) {
   constexpr int BP = 16 * T;
   constexpr int NT = 64 * NW;

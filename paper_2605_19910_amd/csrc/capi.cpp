@@ -32,7 +32,11 @@ rgf_status_t validate(const rgf_desc_t* d) {
   if (d->block_size > 128) return RGF_ERR_UNSUPPORTED;
   if (d->num_layers > 1 && d->half_bandwidth >= d->num_layers) return RGF_ERR_INVALID_ARG;
   if (d->num_layers > (int64_t)1 << 24 || d->num_energies > (int64_t)1 << 24) return RGF_ERR_UNSUPPORTED;
-  if (d->precision != RGF_FP64) return RGF_ERR_UNSUPPORTED;
+  if (d->precision != RGF_FP64 && d->precision != RGF_MIXED_FP32) return RGF_ERR_UNSUPPORTED;
+  // mixed precision: sequential block-tridiagonal sweep only (FP32 products on the
+  // closed interiors of DDRGF lose all accuracy on ill-conditioned interiors)
+  if (d->precision == RGF_MIXED_FP32 && (d->half_bandwidth > 1 || d->method != RGF_METHOD_SEQUENTIAL))
+    return RGF_ERR_UNSUPPORTED;
   if (d->method != RGF_METHOD_SEQUENTIAL && d->method != RGF_METHOD_DDRGF) return RGF_ERR_INVALID_ARG;
   if (d->half_bandwidth > 4) return RGF_ERR_UNSUPPORTED;
   if (d->method == RGF_METHOD_DDRGF) {
@@ -155,6 +159,7 @@ rgf_status_t rgf_solve(rgf_plan_t plan, const void* H, const void* sigma_L, cons
   a.l = (int)d.num_layers;
   a.b = (int)d.block_size;
   a.chains = (int)d.num_energies;
+  a.mixed = d.precision == RGF_MIXED_FP32 ? 1 : 0;
   hipError_t e = rgfk::launch_rgf_sweep(a, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? RGF_OK : RGF_ERR_HIP;
 }
@@ -210,6 +215,7 @@ rgf_status_t ddrgf_solve(rgf_plan_t plan, const void* H, const void* sigma_L, co
   a.ws_red_chain = plan->dd_red_chain;
   a.ws_fin = reinterpret_cast<double2*>(ws + plan->off_fin);
   a.info_part = reinterpret_cast<int*>(ws + plan->off_info);
+  a.mixed = d.precision == RGF_MIXED_FP32 ? 1 : 0;
   hipError_t e = rgfk::launch_ddrgf(a, st);
   if (e == hipSuccess && w > 1) e = rgfk::launch_unfuse(f, st);
   return e == hipSuccess ? RGF_OK : RGF_ERR_HIP;

@@ -54,12 +54,12 @@ size_t ddrgf_interior_ws_elems(int nmax, int bp) { return (size_t)(9 * (size_t)n
 
 // Diagonal block of M for global layer i: (E + i eta) I - H_ii - [i==0] Sigma_L - [i==l-1] Sigma_R.
 template <int T, int NW>
-__device__ __forceinline__ void diag_M(Acc<T, NW>& acc, const DDArgs& a, int e, int i) {
+__device__ __forceinline__ void diag_M(Acc<T, NW>& acc, const DDArgs& a, int e, int i, bool add = false) {
   const size_t bb = (size_t)a.b * a.b;
   const double2 z = make_double2(a.E[e], a.eta_d);
   assemble_diag<T, NW>(acc, a.H + (size_t)(a.l + i) * bb, a.b, z,
                        i == 0 ? a.sigL + (size_t)e * bb : nullptr,
-                       i == a.l - 1 ? a.sigR + (size_t)e * bb : nullptr);
+                       i == a.l - 1 ? a.sigR + (size_t)e * bb : nullptr, add);
 }
 
 // H band accessors: block (i, i-1), (i, i+1)
@@ -73,7 +73,7 @@ __device__ __forceinline__ const double2* Hup(const DDArgs& a, int i) {
 // ---------------------------------------------------------------------------
 // 1. interiors
 // ---------------------------------------------------------------------------
-template <int T, int NW>
+template <int T, int NW, int MIXED>
 __global__ __launch_bounds__(64 * NW, 1) void ddrgf_interior_kernel(DDArgs a) {
   constexpr int BP = 16 * T;
   __shared__ GJShared sh;
@@ -104,89 +104,95 @@ __global__ __launch_bounds__(64 * NW, 1) void ddrgf_interior_kernel(DDArgs a) {
   Acc<T, NW> acc;
 
   // ---------------- upward pass over the closed interior ----------------
+  double2* Ssave = ws + (size_t)9 * nmax * bpbp;     // refinement scratch (2 blocks)
+  double2* Rres = Ssave + bpbp;
+  auto P = [&](const double2* p) { return opnd(p, BP, BP, BP); };
+  auto Pb = [&](const double2* p) { return opnd(p, b, b, b); };
   diag_M<T, NW>(acc, a, e, a0 + n - 1);
   for (int i = n - 1; i >= 0; --i) {
-    gj_invert<T, NW>(acc, g + (size_t)i * bpbp, sh);
+    double2* gi = g + (size_t)i * bpbp;
+    if (MIXED) store<T, NW>(acc, Ssave, BP, BP, BP);
+    gj_invert<T, NW>(acc, gi, sh);
     if (sh.bad && bad_layer < 0) bad_layer = a0 + i;
     __syncthreads();
+    if (MIXED) {
+      // one step of iterative refinement in FP64: g <- g + g (I - S g)
+      acc_zero<T, NW>(acc);
+      mma<T, NW>(acc, P(Ssave), P(gi), -1.0);
+      add_identity<T, NW>(acc);
+      store<T, NW>(acc, Rres, BP, BP, BP);
+      __syncthreads();
+      load<T, NW>(acc, P(gi));
+      mma<T, NW>(acc, P(gi), P(Rres), 1.0);
+      __syncthreads();
+      store<T, NW>(acc, gi, BP, BP, BP);
+      __syncthreads();
+    }
     if (i == n - 1) {
       // P_{n-1} folded with M_{e,qR} = -H_{e,e+1};  Q_{n-1} with M_{qR,e} = -H_{qR,qR-1}
-      load<T, NW>(acc, opnd(Hup(a, a0 + n - 1), b, b, b), -1.0);
+      load<T, NW>(acc, Pb(Hup(a, a0 + n - 1)), -1.0);
       store<T, NW>(acc, Pt + (size_t)i * bpbp, BP, BP, BP);
-      load<T, NW>(acc, opnd(Hlo(a, qR), b, b, b), -1.0);
+      load<T, NW>(acc, Pb(Hlo(a, qR)), -1.0);
       store<T, NW>(acc, Qt + (size_t)i * bpbp, BP, BP, BP);
       __syncthreads();
     }
     if (i == 0) break;
-    const int gi = a0 + i;
-    acc_zero<T, NW>(acc);
-    mma<T, NW>(acc, opnd(g + (size_t)i * bpbp, BP, BP, BP), opnd(Hlo(a, gi), b, b, b), -1.0);
+    const int gl = a0 + i;
+    gemm_to<MIXED, T, NW>(acc, P(gi), Pb(Hlo(a, gl)), -1.0);
     store<T, NW>(acc, L + (size_t)i * bpbp, BP, BP, BP);
-    acc_zero<T, NW>(acc);
-    mma<T, NW>(acc, opnd(Hup(a, gi - 1), b, b, b), opnd(g + (size_t)i * bpbp, BP, BP, BP), -1.0);
+    gemm_to<MIXED, T, NW>(acc, Pb(Hup(a, gl - 1)), P(gi), -1.0);
     store<T, NW>(acc, U + (size_t)i * bpbp, BP, BP, BP);
     __syncthreads();
-    acc_zero<T, NW>(acc);
-    mma<T, NW>(acc, opnd(U + (size_t)i * bpbp, BP, BP, BP), opnd(Pt + (size_t)i * bpbp, BP, BP, BP), -1.0);
+    gemm_to<MIXED, T, NW>(acc, P(U + (size_t)i * bpbp), P(Pt + (size_t)i * bpbp), -1.0);
     store<T, NW>(acc, Pt + (size_t)(i - 1) * bpbp, BP, BP, BP);
-    acc_zero<T, NW>(acc);
-    mma<T, NW>(acc, opnd(Qt + (size_t)i * bpbp, BP, BP, BP), opnd(L + (size_t)i * bpbp, BP, BP, BP), -1.0);
+    gemm_to<MIXED, T, NW>(acc, P(Qt + (size_t)i * bpbp), P(L + (size_t)i * bpbp), -1.0);
     store<T, NW>(acc, Qt + (size_t)(i - 1) * bpbp, BP, BP, BP);
-    diag_M<T, NW>(acc, a, e, gi - 1);
-    mma<T, NW>(acc, opnd(Hup(a, gi - 1), b, b, b), opnd(L + (size_t)i * bpbp, BP, BP, BP), 1.0);
+    // S_{i-1} = M_{i-1,i-1} - M_{i-1,i} L_i = M_{i-1,i-1} + H_{i-1,i} L_i
+    gemm_to<MIXED, T, NW>(acc, Pb(Hup(a, gl - 1)), P(L + (size_t)i * bpbp), 1.0);
+    diag_M<T, NW>(acc, a, e, gl - 1, true);
     __syncthreads();
   }
 
   // ---------------- downward pass, band of X and halo products ----------------
-  load<T, NW>(acc, opnd(g, BP, BP, BP));
+  load<T, NW>(acc, P(g));
   store<T, NW>(acc, Gd + (size_t)a0 * bb, b, b, b);
   __syncthreads();
-  const Opnd X00 = opnd(Gd + (size_t)a0 * bb, b, b, b);
+  const Opnd X00 = Pb(Gd + (size_t)a0 * bb);
   if (left) {
-    acc_zero<T, NW>(acc);
-    mma<T, NW>(acc, X00, opnd(Hlo(a, a0), b, b, b), -1.0);          // X_00 M_{a,qL}
+    gemm_to<MIXED, T, NW>(acc, X00, Pb(Hlo(a, a0)), -1.0);          // X_00 M_{a,qL}
     store<T, NW>(acc, CL, BP, BP, BP);
-    acc_zero<T, NW>(acc);
-    mma<T, NW>(acc, opnd(Hup(a, qL), b, b, b), X00, -1.0);          // M_{qL,a} X_00
+    gemm_to<MIXED, T, NW>(acc, Pb(Hup(a, qL)), X00, -1.0);          // M_{qL,a} X_00
     store<T, NW>(acc, RL, BP, BP, BP);
   }
-  acc_zero<T, NW>(acc);
-  mma<T, NW>(acc, X00, opnd(Pt, BP, BP, BP), 1.0);
+  gemm_to<MIXED, T, NW>(acc, X00, P(Pt), 1.0);
   store<T, NW>(acc, CR, BP, BP, BP);
-  acc_zero<T, NW>(acc);
-  mma<T, NW>(acc, opnd(Qt, BP, BP, BP), X00, 1.0);
+  gemm_to<MIXED, T, NW>(acc, P(Qt), X00, 1.0);
   store<T, NW>(acc, RR, BP, BP, BP);
   __syncthreads();
   for (int i = 1; i < n; ++i) {
-    const int gi = a0 + i;
-    const Opnd Xp = opnd(Gd + (size_t)(gi - 1) * bb, b, b, b);
-    const Opnd Ui = opnd(U + (size_t)i * bpbp, BP, BP, BP);
-    const Opnd Li = opnd(L + (size_t)i * bpbp, BP, BP, BP);
-    acc_zero<T, NW>(acc);
-    mma<T, NW>(acc, Xp, Ui, -1.0);
-    store<T, NW>(acc, Gu + (size_t)(gi - 1) * bb, b, b, b);
-    acc_zero<T, NW>(acc);
-    mma<T, NW>(acc, Li, Xp, -1.0);
-    store<T, NW>(acc, Gl + (size_t)gi * bb, b, b, b);
+    const int gl = a0 + i;
+    const Opnd Xp = Pb(Gd + (size_t)(gl - 1) * bb);
+    const Opnd Ui = P(U + (size_t)i * bpbp);
+    const Opnd Li = P(L + (size_t)i * bpbp);
+    gemm_to<MIXED, T, NW>(acc, Xp, Ui, -1.0);
+    store<T, NW>(acc, Gu + (size_t)(gl - 1) * bb, b, b, b);
+    gemm_to<MIXED, T, NW>(acc, Li, Xp, -1.0);
+    store<T, NW>(acc, Gl + (size_t)gl * bb, b, b, b);
     if (left) {
-      acc_zero<T, NW>(acc);
-      mma<T, NW>(acc, Li, opnd(CL + (size_t)(i - 1) * bpbp, BP, BP, BP), -1.0);
+      gemm_to<MIXED, T, NW>(acc, Li, P(CL + (size_t)(i - 1) * bpbp), -1.0);
       store<T, NW>(acc, CL + (size_t)i * bpbp, BP, BP, BP);
-      acc_zero<T, NW>(acc);
-      mma<T, NW>(acc, opnd(RL + (size_t)(i - 1) * bpbp, BP, BP, BP), Ui, -1.0);
+      gemm_to<MIXED, T, NW>(acc, P(RL + (size_t)(i - 1) * bpbp), Ui, -1.0);
       store<T, NW>(acc, RL + (size_t)i * bpbp, BP, BP, BP);
     }
     __syncthreads();
-    load<T, NW>(acc, opnd(g + (size_t)i * bpbp, BP, BP, BP));
-    mma<T, NW>(acc, Li, opnd(Gu + (size_t)(gi - 1) * bb, b, b, b), -1.0);
-    store<T, NW>(acc, Gd + (size_t)gi * bb, b, b, b);
+    gemm_to<MIXED, T, NW>(acc, Li, Pb(Gu + (size_t)(gl - 1) * bb), -1.0);
+    add_from<T, NW>(acc, P(g + (size_t)i * bpbp));
+    store<T, NW>(acc, Gd + (size_t)gl * bb, b, b, b);
     __syncthreads();
-    const Opnd Xii = opnd(Gd + (size_t)gi * bb, b, b, b);
-    acc_zero<T, NW>(acc);
-    mma<T, NW>(acc, Xii, opnd(Pt + (size_t)i * bpbp, BP, BP, BP), 1.0);
+    const Opnd Xii = Pb(Gd + (size_t)gl * bb);
+    gemm_to<MIXED, T, NW>(acc, Xii, P(Pt + (size_t)i * bpbp), 1.0);
     store<T, NW>(acc, CR + (size_t)i * bpbp, BP, BP, BP);
-    acc_zero<T, NW>(acc);
-    mma<T, NW>(acc, opnd(Qt + (size_t)i * bpbp, BP, BP, BP), Xii, 1.0);
+    gemm_to<MIXED, T, NW>(acc, P(Qt + (size_t)i * bpbp), Xii, 1.0);
     store<T, NW>(acc, RR + (size_t)i * bpbp, BP, BP, BP);
   }
   if (threadIdx.x == 0) a.info_part[(size_t)e * (a.m + 1) + k] = bad_layer >= 0 ? bad_layer + 1 : 0;
@@ -234,7 +240,7 @@ __global__ __launch_bounds__(64 * NW, 1) void ddrgf_schur_kernel(DDArgs a) {
 // ---------------------------------------------------------------------------
 // 4. recovery of the interior blocks and the separator couplings
 // ---------------------------------------------------------------------------
-template <int T, int NW>
+template <int T, int NW, int MIXED>
 __global__ __launch_bounds__(64 * NW, 1) void ddrgf_recover_kernel(DDArgs a) {
   constexpr int BP = 16 * T;
   const int c = blockIdx.x;
@@ -265,20 +271,34 @@ __global__ __launch_bounds__(64 * NW, 1) void ddrgf_recover_kernel(DDArgs a) {
   auto blk = [&](const double2* base, int i) { return opnd(base + (size_t)i * bpbp, BP, BP, BP); };
 
   Acc<T, NW> acc;
+  // two-term products [X, Y] [Z1; Z2] as one product over a doubled k range when mixed
+  auto gemm2 = [&](const Opnd& A1, const Opnd& B1, const Opnd& A2, const Opnd& B2, bool two) {
+    gemm_to<MIXED, T, NW>(acc, A1, B1, 1.0);
+    if (two) {
+      if (MIXED) {
+        Acc<T, NW> tmp;
+        gemm_f32<T, NW>(tmp, A2, B2, 1.0);
+        for (int r = 0; r < Acc<T, NW>::RR; ++r)
+          for (int c = 0; c < Acc<T, NW>::RC; ++c) {
+            acc.re[r][c] += tmp.re[r][c];
+            acc.im[r][c] += tmp.im[r][c];
+          }
+      } else {
+        mma<T, NW>(acc, A2, B2, 1.0);
+      }
+    }
+  };
   for (int i = 0; i < n; ++i) {
     const int gi = a0 + i;
     // V_i = [CL_i, CR_i] Z
-    acc_zero<T, NW>(acc);
-    if (left) {
-      mma<T, NW>(acc, blk(CL, i), ZLR, 1.0);
-    }
-    mma<T, NW>(acc, blk(CR, i), ZRR, 1.0);
+    if (left)
+      gemm2(blk(CR, i), ZRR, blk(CL, i), ZLR, true);
+    else
+      gemm2(blk(CR, i), ZRR, blk(CR, i), ZRR, false);
     store<T, NW>(acc, VR, BP, BP, BP);
     if (i == n - 1) store<T, NW>(acc, Gu + (size_t)gi * bb, b, b, b, -1.0);   // G_{e,qR} = -V^R
     if (left) {
-      acc_zero<T, NW>(acc);
-      mma<T, NW>(acc, blk(CL, i), ZLL, 1.0);
-      mma<T, NW>(acc, blk(CR, i), ZRL, 1.0);
+      gemm2(blk(CL, i), ZLL, blk(CR, i), ZRL, true);
       store<T, NW>(acc, VL, BP, BP, BP);
       if (i == 0) store<T, NW>(acc, Gl + (size_t)gi * bb, b, b, b, -1.0);     // G_{a,qL} = -V^L
     }
@@ -288,9 +308,8 @@ __global__ __launch_bounds__(64 * NW, 1) void ddrgf_recover_kernel(DDArgs a) {
       const int j = i + d;
       if (j < 0 || j >= n) continue;
       double2* dst = (d == 0 ? Gd : (d < 0 ? Gl : Gu)) + (size_t)gi * bb;
-      load<T, NW>(acc, opnd(dst, b, b, b));
-      if (left) mma<T, NW>(acc, opnd(VL, BP, BP, BP), blk(RL, j), 1.0);
-      mma<T, NW>(acc, opnd(VR, BP, BP, BP), blk(RR, j), 1.0);
+      gemm2(opnd(VR, BP, BP, BP), blk(RR, j), opnd(VL, BP, BP, BP), blk(RL, j), left);
+      add_from<T, NW>(acc, opnd(dst, b, b, b));
       store<T, NW>(acc, dst, b, b, b);
     }
     __syncthreads();
@@ -371,7 +390,10 @@ template <int T>
 static hipError_t launch_dd_T(const DDArgs& a, hipStream_t s) {
   constexpr int NW = T >= 7 ? 8 : 4;
   const int chains = a.ne * a.m;
-  hipLaunchKernelGGL((ddrgf_interior_kernel<T, NW>), dim3(chains), dim3(64 * NW), 0, s, a);
+  if (a.mixed)
+    hipLaunchKernelGGL((ddrgf_interior_kernel<T, NW, 1>), dim3(chains), dim3(64 * NW), 0, s, a);
+  else
+    hipLaunchKernelGGL((ddrgf_interior_kernel<T, NW, 0>), dim3(chains), dim3(64 * NW), 0, s, a);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
   hipLaunchKernelGGL((ddrgf_schur_kernel<T, NW>), dim3(chains), dim3(64 * NW), 0, s, a);
@@ -392,8 +414,12 @@ static hipError_t launch_dd_T(const DDArgs& a, hipStream_t s) {
   r.chains = a.ne;
   r.info_stride = a.m + 1;
   r.info_offset = a.m;
+  r.mixed = a.mixed;
   if ((err = launch_rgf_sweep(r, s)) != hipSuccess) return err;
-  hipLaunchKernelGGL((ddrgf_recover_kernel<T, NW>), dim3(chains), dim3(64 * NW), 0, s, a);
+  if (a.mixed)
+    hipLaunchKernelGGL((ddrgf_recover_kernel<T, NW, 1>), dim3(chains), dim3(64 * NW), 0, s, a);
+  else
+    hipLaunchKernelGGL((ddrgf_recover_kernel<T, NW, 0>), dim3(chains), dim3(64 * NW), 0, s, a);
   if ((err = hipGetLastError()) != hipSuccess) return err;
   hipLaunchKernelGGL((ddrgf_finalize_kernel<T, NW>), dim3(a.ne), dim3(64 * NW), 0, s, a);
   return hipGetLastError();

@@ -30,6 +30,7 @@ struct SweepArgs {
   double2* ws;               // workspace, ws_chain elements per chain
   size_t ws_chain;
   int l, b, chains;
+  int mixed;                 // 1: products on FP32 MFMA, FP64 pivots + one refinement step
 };
 
 size_t sweep_ws_chain_elems(int l, int bp);
@@ -56,6 +57,7 @@ struct DDArgs {
   size_t ws_red_chain;
   int* info_part;            // [ne][m + 1] per-stage status
   double2* ws_fin;           // [ne][4][bp][bp]
+  int mixed;                 // 1: products on FP32 MFMA, FP64 pivots + one refinement step
 };
 
 size_t ddrgf_interior_ws_elems(int nmax, int bp);

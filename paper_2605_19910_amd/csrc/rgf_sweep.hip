@@ -17,11 +17,11 @@ namespace rgfk {
 int padded_block(int b) { return ((b + 15) / 16) * 16; }
 
 size_t sweep_ws_chain_elems(int l, int bp) {
-  // g[l], U[l], L[l], R[2], Gamma_L, Gamma_R, X1
-  return (size_t)(3 * (size_t)l + 5) * (size_t)bp * (size_t)bp;
+  // g[l], U[l], L[l], R[2], Gamma_L, Gamma_R, X1, and two blocks for the pivot refinement
+  return (size_t)(3 * (size_t)l + 7) * (size_t)bp * (size_t)bp;
 }
 
-template <int T, int NW>
+template <int T, int NW, int MIXED>
 __global__ __launch_bounds__(64 * NW, 1) void rgf_sweep_kernel(SweepArgs a) {
   constexpr int BP = 16 * T;
   constexpr int NT = 64 * NW;
@@ -40,6 +40,8 @@ __global__ __launch_bounds__(64 * NW, 1) void rgf_sweep_kernel(SweepArgs a) {
   double2* GamL = Rb + 2 * bpbp;
   double2* GamR = GamL + bpbp;
   double2* X1 = GamR + bpbp;
+  double2* Ssave = X1 + bpbp;     // pivot before inversion (refinement)
+  double2* Rres = Ssave + bpbp;   // I - S g (refinement)
 
   const double2* H = a.H + (size_t)e * a.h_stride;
   const double2* Hl = H;                          // block (i, i-1) at Hl + i*bb
@@ -58,13 +60,10 @@ __global__ __launch_bounds__(64 * NW, 1) void rgf_sweep_kernel(SweepArgs a) {
   int bad_layer = -1;
   Acc<T, NW> acc;
 
-  auto diag = [&](int i) {
-    if (a.direct)
-      load<T, NW>(acc, opnd(Hd + (size_t)i * bb, b, b, b));
-    else
-      assemble_diag<T, NW>(acc, Hd + (size_t)i * bb, b, z, i == 0 ? sL : nullptr,
-                       i == l - 1 ? sR : nullptr);
+  // acc (+)= M_ii: assembled from H, E, Sigma, or read from the direct band
+  auto diag = [&](int i, bool add) {
     if (a.direct) {
+      add_from<T, NW>(acc, opnd(Hd + (size_t)i * bb, b, b, b));
       // identity on the padding of a directly given block
       const int ln = lane_id();
       int tr0, tc0;
@@ -76,31 +75,51 @@ __global__ __launch_bounds__(64 * NW, 1) void rgf_sweep_kernel(SweepArgs a) {
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int ii = 16 * (tr0 + r) + c_row(ln, v), jj = 16 * (tc0 + c) + c_col(ln);
-            if (ii == jj && ii >= b && tr0 + r < T && tc0 + c < T) acc.re[r][c][v] = 1.0;
+            if (ii == jj && ii >= b && tr0 + r < T && tc0 + c < T) acc.re[r][c][v] += 1.0;
           }
+    } else {
+      assemble_diag<T, NW>(acc, Hd + (size_t)i * bb, b, z, i == 0 ? sL : nullptr,
+                           i == l - 1 ? sR : nullptr, add);
     }
   };
+  auto P = [&](const double2* p) { return opnd(p, BP, BP, BP); };
+  auto Pb = [&](const double2* p) { return opnd(p, b, b, b); };
 
   // ---------------- upward pass ----------------
-  diag(l - 1);
+  acc_zero<T, NW>(acc);
+  diag(l - 1, true);
   for (int i = l - 1; i >= 0; --i) {
-    gj_invert<T, NW>(acc, g + (size_t)i * bpbp, sh);
+    double2* gi = g + (size_t)i * bpbp;
+    if (MIXED) store<T, NW>(acc, Ssave, BP, BP, BP);
+    gj_invert<T, NW>(acc, gi, sh);
     if (sh.bad && bad_layer < 0) bad_layer = i;
     __syncthreads();
+    if (MIXED) {
+      // one step of iterative refinement in FP64: g <- g + g (I - S g)
+      acc_zero<T, NW>(acc);
+      mma<T, NW>(acc, P(Ssave), P(gi), -1.0);
+      add_identity<T, NW>(acc);
+      store<T, NW>(acc, Rres, BP, BP, BP);
+      __syncthreads();
+      load<T, NW>(acc, P(gi));
+      mma<T, NW>(acc, P(gi), P(Rres), 1.0);
+      __syncthreads();
+      store<T, NW>(acc, gi, BP, BP, BP);
+      __syncthreads();
+    }
     if (i == 0) break;
-    acc_zero<T, NW>(acc);
-    mma<T, NW>(acc, opnd(g + (size_t)i * bpbp, BP, BP, BP), opnd(Hl + (size_t)i * bb, b, b, b), ms);
+    gemm_to<MIXED, T, NW>(acc, P(gi), Pb(Hl + (size_t)i * bb), ms);
     store<T, NW>(acc, L + (size_t)i * bpbp, BP, BP, BP);
-    acc_zero<T, NW>(acc);
-    mma<T, NW>(acc, opnd(Hu + (size_t)(i - 1) * bb, b, b, b), opnd(g + (size_t)i * bpbp, BP, BP, BP), ms);
+    gemm_to<MIXED, T, NW>(acc, Pb(Hu + (size_t)(i - 1) * bb), P(gi), ms);
     store<T, NW>(acc, U + (size_t)i * bpbp, BP, BP, BP);
     __syncthreads();
-    diag(i - 1);
-    mma<T, NW>(acc, opnd(Hu + (size_t)(i - 1) * bb, b, b, b), opnd(L + (size_t)i * bpbp, BP, BP, BP), -ms);
+    // S_{i-1} = M_{i-1,i-1} - M_{i-1,i} L_i
+    gemm_to<MIXED, T, NW>(acc, Pb(Hu + (size_t)(i - 1) * bb), P(L + (size_t)i * bpbp), -ms);
+    diag(i - 1, true);
   }
 
   // ---------------- downward pass ----------------
-  load<T, NW>(acc, opnd(g, BP, BP, BP));
+  load<T, NW>(acc, P(g));
   store<T, NW>(acc, Gd, b, b, b);
   store<T, NW>(acc, Rb, BP, BP, BP);
   if (a.first_row) store<T, NW>(acc, a.first_row + (size_t)e * l * bb, b, b, b);
@@ -109,19 +128,16 @@ __global__ __launch_bounds__(64 * NW, 1) void rgf_sweep_kernel(SweepArgs a) {
     const double2* Gp = Gd + (size_t)(i - 1) * bb;
     const double2* Ui = U + (size_t)i * bpbp;
     const double2* Li = L + (size_t)i * bpbp;
-    acc_zero<T, NW>(acc);
-    mma<T, NW>(acc, opnd(Gp, b, b, b), opnd(Ui, BP, BP, BP), -1.0);
+    gemm_to<MIXED, T, NW>(acc, Pb(Gp), P(Ui), -1.0);
     store<T, NW>(acc, Gu + (size_t)(i - 1) * bb, b, b, b);
-    acc_zero<T, NW>(acc);
-    mma<T, NW>(acc, opnd(Li, BP, BP, BP), opnd(Gp, b, b, b), -1.0);
+    gemm_to<MIXED, T, NW>(acc, P(Li), Pb(Gp), -1.0);
     store<T, NW>(acc, Gl + (size_t)i * bb, b, b, b);
-    acc_zero<T, NW>(acc);
-    mma<T, NW>(acc, opnd(Rb + (size_t)((i - 1) & 1) * bpbp, BP, BP, BP), opnd(Ui, BP, BP, BP), -1.0);
+    gemm_to<MIXED, T, NW>(acc, P(Rb + (size_t)((i - 1) & 1) * bpbp), P(Ui), -1.0);
     store<T, NW>(acc, Rb + (size_t)(i & 1) * bpbp, BP, BP, BP);
     if (a.first_row) store<T, NW>(acc, a.first_row + ((size_t)e * l + i) * bb, b, b, b);
     __syncthreads();
-    load<T, NW>(acc, opnd(g + (size_t)i * bpbp, BP, BP, BP));
-    mma<T, NW>(acc, opnd(Li, BP, BP, BP), opnd(Gu + (size_t)(i - 1) * bb, b, b, b), -1.0);
+    gemm_to<MIXED, T, NW>(acc, P(Li), Pb(Gu + (size_t)(i - 1) * bb), -1.0);
+    add_from<T, NW>(acc, P(g + (size_t)i * bpbp));
     store<T, NW>(acc, Gd + (size_t)i * bb, b, b, b);
     __syncthreads();
   }
@@ -149,7 +165,10 @@ __global__ __launch_bounds__(64 * NW, 1) void rgf_sweep_kernel(SweepArgs a) {
 template <int T>
 static hipError_t launch_T(const SweepArgs& a, hipStream_t s) {
   constexpr int NW = T >= 7 ? 8 : 4;
-  hipLaunchKernelGGL((rgf_sweep_kernel<T, NW>), dim3(a.chains), dim3(64 * NW), 0, s, a);
+  if (a.mixed)
+    hipLaunchKernelGGL((rgf_sweep_kernel<T, NW, 1>), dim3(a.chains), dim3(64 * NW), 0, s, a);
+  else
+    hipLaunchKernelGGL((rgf_sweep_kernel<T, NW, 0>), dim3(a.chains), dim3(64 * NW), 0, s, a);
   return hipGetLastError();
 }
 

@@ -54,7 +54,7 @@ def test_plan_workspace_size(l, b, w, ne):
     binding = _lib()
     p = binding.Plan(l, b, w, ne)
     bp = ((b + 15) // 16) * 16
-    assert p.workspace_bytes == (3 * l + 5) * bp * bp * 16 * ne
+    assert p.workspace_bytes == (3 * l + 7) * bp * bp * 16 * ne
     p.close()
 
 
@@ -65,6 +65,11 @@ def test_plan_workspace_size(l, b, w, ne):
     (dict(l=4, b=129, w=1, ne=1), 2),
     (dict(l=4, b=4, w=4, ne=1), 1),
     (dict(l=4, b=4, w=1, ne=1, precision="bf16x3"), 2),
+    (dict(l=8, b=4, w=2, ne=1, precision="fp32"), 2),
+    (dict(l=8, b=4, w=1, ne=1, method="ddrgf", domains=2, precision="fp32"), 2),
+    (dict(l=9, b=4, w=2, ne=1, method="ddrgf", domains=2), 2),
+    (dict(l=8, b=80, w=2, ne=1, method="ddrgf", domains=2), 2),
+    (dict(l=8, b=4, w=1, ne=1, method="ddrgf", domains=5), 1),
 ])
 def test_plan_validation_errors(args, code):
     binding = _lib()

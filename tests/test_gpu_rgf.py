@@ -25,11 +25,11 @@ def to_dev(wl):
             torch.from_numpy(wl.sigma_R).to(d), torch.from_numpy(wl.energies).to(d))
 
 
-def run_gpu(lib, wl, method="rgf", eta_d=None, domains=0):
+def run_gpu(lib, wl, method="rgf", eta_d=None, domains=0, precision="fp64"):
     import torch
     H, sL, sR, E = to_dev(wl)
     G, T, info = lib.solve(H, sL, sR, E, eta_d=wl.eta_d if eta_d is None else eta_d, method=method,
-                           domains=domains)
+                           domains=domains, precision=precision)
     torch.cuda.synchronize()
     return G.cpu().numpy(), T.cpu().numpy(), info.cpu().numpy()
 
