@@ -111,6 +111,61 @@ rgf_status_t ddrgf_solve(rgf_plan_t plan, const void* H, const void* sigma_L, co
                          const double* energies, double eta_d, void* G, double* T, int32_t* info,
                          void* workspace, size_t workspace_bytes, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Batched launch over systems ("devices") of uneven size
+ * ---------------------------------------------------------------------------
+ * Each device d has its own block-tridiagonal band H_d (l_d layers of b_d orbitals,
+ * b_d in {32, 64, 96, 128}) and its own energies; one instance = one (device,
+ * energy) pair.  All instances run in ONE persistent kernel: workgroups pull
+ * instances from a work queue ordered by the plan's schedule and run the whole
+ * sweep of each (Algorithm 1); the outputs are T(E) and the diagonal blocks G_ii
+ * (the band's off-diagonal blocks are not written).  The first solve on a
+ * non-default stream captures the launch into a hipGraph that later solves with the
+ * same device table, workspace and stream replay. */
+
+/* Host-side shape of one device. */
+typedef struct {
+  int64_t num_layers;     /* l_d >= 2 */
+  int64_t block_size;     /* b_d in {32, 64, 96, 128} */
+  int64_t num_energies;   /* nE_d >= 1 */
+} rgf_batch_shape_t;
+
+/* Device-side table entry of one device (the caller fills an array of these in
+ * device memory; all pointers are device pointers). */
+typedef struct {
+  const void* H;            /* band [3][l][b][b] */
+  const void* sigma_L;      /* [nE][b][b] */
+  const void* sigma_R;      /* [nE][b][b] */
+  const double* energies;   /* [nE] */
+  void* G_diag;             /* out [nE][l][b][b]: diagonal blocks of G */
+  double* T;                /* out [nE], may be NULL */
+  int32_t* info;            /* out [nE], as for rgf_solve */
+  int32_t num_layers;       /* must equal the plan's shape */
+  int32_t block_size;
+} rgf_batch_device_t;
+
+typedef enum {
+  RGF_SCHEDULE_LONGEST_FIRST = 0,  /* instances by decreasing l*b^3 */
+  RGF_SCHEDULE_INPUT_ORDER = 1,    /* device by device, energy by energy */
+  RGF_SCHEDULE_INTERLEAVED = 2     /* longest first within each block size, sizes interleaved */
+} rgf_schedule_t;
+
+/* Build a batched plan.  shapes: host array [num_devices].  precision: RGF_FP64 or
+ * RGF_MIXED_FP32.  grid: persistent workgroups (0 = one per compute unit of the
+ * current device).  Unlike the other plans this one owns a small device array (the
+ * work queue, 3 ints per instance), allocated here and freed by rgf_plan_destroy;
+ * creating it needs a visible GPU.  *workspace_bytes: one workspace slot per
+ * persistent workgroup, sized for the largest device, plus the queue counter. */
+rgf_status_t rgf_batched_plan_create(int64_t num_devices, const rgf_batch_shape_t* shapes,
+                                     int32_t precision, int32_t schedule, int32_t grid,
+                                     rgf_plan_t* plan, size_t* workspace_bytes);
+
+/* Run every instance of the plan.  devices: DEVICE array [num_devices] of table
+ * entries.  Numerical failures are reported per instance through each device's
+ * info[].  Calls on one plan from several host threads are serialised. */
+rgf_status_t rgf_batched_solve(rgf_plan_t plan, const rgf_batch_device_t* devices, double eta_d,
+                               void* workspace, size_t workspace_bytes, void* stream);
+
 /* Static text of a status code. */
 const char* rgf_status_string(rgf_status_t status);
 

@@ -5,6 +5,8 @@ The computation lives in the HIP library ``lib/librgf.so`` (C ABI in
 it.  Importing this package does not load the library; the first call does, and it
 fails loudly when the library has not been built.
 """
-from .binding import Plan, RgfError, load, solve  # noqa: F401
+from .binding import (BatchedPlan, Plan, RgfError, device_table, load, rgf_batched_solve,  # noqa: F401
+                      solve, solve_batched)
 
-__all__ = ["Plan", "RgfError", "load", "solve"]
+__all__ = ["BatchedPlan", "Plan", "RgfError", "device_table", "load", "rgf_batched_solve", "solve",
+           "solve_batched"]

@@ -37,6 +37,18 @@ class RgfDesc(ctypes.Structure):
     ]
 
 
+class BatchShape(ctypes.Structure):
+    _fields_ = [("num_layers", ctypes.c_int64), ("block_size", ctypes.c_int64),
+                ("num_energies", ctypes.c_int64)]
+
+
+# layout of rgf_batch_device_t: seven device pointers and two int32
+BATCH_DEVICE_DTYPE = [("H", "<u8"), ("sigma_L", "<u8"), ("sigma_R", "<u8"), ("energies", "<u8"),
+                      ("G_diag", "<u8"), ("T", "<u8"), ("info", "<u8"), ("num_layers", "<i4"),
+                      ("block_size", "<i4")]
+SCHEDULE = {"longest_first": 0, "input_order": 1, "interleaved": 2}
+
+
 class RgfError(RuntimeError):
     def __init__(self, fn: str, code: int):
         super().__init__(f"{fn}: {STATUS.get(code, 'unknown status')} (code {code})")
@@ -66,6 +78,12 @@ def load() -> ctypes.CDLL:
         f = getattr(lib, fn)
         f.argtypes = list(_SOLVE_ARGS)
         f.restype = ctypes.c_int
+    lib.rgf_batched_plan_create.argtypes = [ctypes.c_int64, ctypes.POINTER(BatchShape), ctypes.c_int32,
+                                            ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(_VP),
+                                            ctypes.POINTER(ctypes.c_size_t)]
+    lib.rgf_batched_plan_create.restype = ctypes.c_int
+    lib.rgf_batched_solve.argtypes = [_VP, _VP, ctypes.c_double, _VP, ctypes.c_size_t, _VP]
+    lib.rgf_batched_solve.restype = ctypes.c_int
     lib.rgf_status_string.argtypes = [ctypes.c_int]
     lib.rgf_status_string.restype = ctypes.c_char_p
     lib.rgf_version.argtypes = []
@@ -161,3 +179,81 @@ def solve(H, sigma_L, sigma_R, energies, eta_d: float = 0.0, method: str = "rgf"
     else:
         rgf_solve(plan, H, sigma_L, sigma_R, energies, eta_d, G, T, info, workspace, stream)
     return G, T, info
+
+
+# ----------------------------------------------------------------------------
+# Batched launch over devices of uneven size
+# ----------------------------------------------------------------------------
+
+class BatchedPlan:
+    """Owning wrapper of a batched rgf_plan_t (rgf_batched_plan_create)."""
+
+    def __init__(self, shapes, precision: str = "fp64", schedule: str = "longest_first", grid: int = 0):
+        self.lib = load()
+        arr = (BatchShape * len(shapes))(*[BatchShape(int(l), int(b), int(ne)) for (l, b, ne) in shapes])
+        self.handle = _VP()
+        ws = ctypes.c_size_t(0)
+        st = self.lib.rgf_batched_plan_create(len(shapes), arr, PRECISION[precision], SCHEDULE[schedule],
+                                              int(grid), ctypes.byref(self.handle), ctypes.byref(ws))
+        if st != RGF_OK:
+            raise RgfError("rgf_batched_plan_create", st)
+        self.workspace_bytes = int(ws.value)
+        self.shapes = [tuple(int(v) for v in sh) for sh in shapes]
+        self.precision, self.schedule, self.grid = precision, schedule, grid
+
+    def close(self):
+        if self.handle:
+            self.lib.rgf_plan_destroy(self.handle)
+            self.handle = _VP()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def device_table(entries, device):
+    """Device array of rgf_batch_device_t from a list of dicts with torch tensors
+    H, sigma_L, sigma_R, energies, G_diag, T (or None), info."""
+    import numpy as np
+    import torch
+    rec = np.zeros(len(entries), dtype=BATCH_DEVICE_DTYPE)
+    for k, d in enumerate(entries):
+        rec[k] = (d["H"].data_ptr(), d["sigma_L"].data_ptr(), d["sigma_R"].data_ptr(),
+                  d["energies"].data_ptr(), d["G_diag"].data_ptr(),
+                  0 if d.get("T") is None else d["T"].data_ptr(), d["info"].data_ptr(),
+                  d["H"].shape[1], d["H"].shape[2])
+    return torch.from_numpy(rec.view(np.uint8).copy()).to(device)
+
+
+def rgf_batched_solve(plan: BatchedPlan, table, eta_d: float, workspace, stream: int = 0) -> None:
+    st = plan.lib.rgf_batched_solve(plan.handle, table.data_ptr(), float(eta_d), workspace.data_ptr(),
+                                    workspace.numel() * workspace.element_size(), stream)
+    if st != RGF_OK:
+        raise RgfError("rgf_batched_solve", st)
+
+
+def solve_batched(systems, eta_d: float = 0.0, precision: str = "fp64", schedule: str = "longest_first",
+                  grid: int = 0, plan: Optional[BatchedPlan] = None, stream=None):
+    """systems: list of (H [3, l, b, b], sigma_L [nE, b, b], sigma_R, energies [nE]) GPU tensors.
+    Runs every (system, energy) instance in one persistent launch; returns a list of
+    (G_diag [nE, l, b, b], T [nE], info [nE]) per system."""
+    import torch
+    dev = systems[0][0].device
+    shapes = [(H.shape[1], H.shape[2], E.shape[0]) for (H, _, _, E) in systems]
+    if plan is None:
+        plan = BatchedPlan(shapes, precision=precision, schedule=schedule, grid=grid)
+    outs, entries = [], []
+    for (H, sL, sR, E) in systems:
+        l, b, ne = H.shape[1], H.shape[2], E.shape[0]
+        G = torch.empty((ne, l, b, b), dtype=torch.complex128, device=dev)
+        T = torch.empty((ne,), dtype=torch.float64, device=dev)
+        info = torch.empty((ne,), dtype=torch.int32, device=dev)
+        outs.append((G, T, info))
+        entries.append(dict(H=H, sigma_L=sL, sigma_R=sR, energies=E, G_diag=G, T=T, info=info))
+    table = device_table(entries, dev)
+    ws = torch.empty((plan.workspace_bytes,), dtype=torch.uint8, device=dev)
+    s = stream if stream is not None else torch.cuda.current_stream(dev)
+    rgf_batched_solve(plan, table, eta_d, ws, s.cuda_stream)
+    return outs

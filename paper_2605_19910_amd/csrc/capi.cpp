@@ -1,5 +1,8 @@
 // C ABI: plan validation, workspace layout and dispatch to the HIP kernels.
+#include <algorithm>
+#include <mutex>
 #include <new>
+#include <vector>
 
 #include <hip/hip_runtime.h>
 
@@ -17,6 +20,20 @@ struct rgf_plan_s {
   // w > 1 DDRGF: super-block copies of the inputs and of the output band
   int fl, fb;                    // super-layers and super-block size of the DDRGF system
   size_t off_hf, off_slf, off_srf, off_gf, off_inff;
+  // batched plans
+  int batched = 0;
+  std::vector<rgf_batch_shape_t> shapes;
+  int n_items = 0, grid = 0;
+  int* d_index = nullptr;        // device: queue[n], inst_dev[n], inst_energy[n]
+  size_t ws_slot = 0;
+  std::mutex mu;                 // guards the cached graph
+  bool has_graph = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  const void* g_devs = nullptr;
+  void* g_ws = nullptr;
+  double g_eta = 0.0;
+  hipStream_t g_stream = nullptr;
 };
 
 namespace {
@@ -108,15 +125,154 @@ rgf_status_t rgf_plan_create(const rgf_desc_t* desc, rgf_plan_t* plan, size_t* w
 }
 
 rgf_status_t rgf_plan_destroy(rgf_plan_t plan) {
+  if (!plan) return RGF_OK;
+  if (plan->has_graph) {
+    hipGraphExecDestroy(plan->exec);
+    hipGraphDestroy(plan->graph);
+  }
+  if (plan->d_index) hipFree(plan->d_index);
   delete plan;
   return RGF_OK;
+}
+
+rgf_status_t rgf_batched_plan_create(int64_t num_devices, const rgf_batch_shape_t* shapes,
+                                     int32_t precision, int32_t schedule, int32_t grid,
+                                     rgf_plan_t* plan, size_t* workspace_bytes) {
+  if (!plan) return RGF_ERR_INVALID_ARG;
+  *plan = nullptr;
+  if (num_devices < 1 || num_devices > (1 << 20) || !shapes) return RGF_ERR_INVALID_ARG;
+  if (precision != RGF_FP64 && precision != RGF_MIXED_FP32) return RGF_ERR_UNSUPPORTED;
+  if (schedule < 0 || schedule > 2 || grid < 0) return RGF_ERR_INVALID_ARG;
+  struct Item { int dev, en; double cost; int b; };
+  std::vector<Item> items;
+  size_t slot = 0;
+  for (int64_t d = 0; d < num_devices; ++d) {
+    const rgf_batch_shape_t& sh = shapes[d];
+    if (sh.num_layers < 1 || sh.num_layers > (1 << 20) || sh.num_energies < 1 || sh.num_energies > (1 << 20))
+      return RGF_ERR_INVALID_ARG;
+    if (sh.block_size != 32 && sh.block_size != 64 && sh.block_size != 96 && sh.block_size != 128)
+      return RGF_ERR_UNSUPPORTED;
+    slot = std::max(slot, rgfk::sweep_ws_chain_elems((int)sh.num_layers, (int)sh.block_size));
+    const double cost = (double)sh.num_layers * (double)sh.block_size * sh.block_size * sh.block_size;
+    for (int64_t e = 0; e < sh.num_energies; ++e) items.push_back({(int)d, (int)e, cost, (int)sh.block_size});
+  }
+  if (items.size() > (size_t)1 << 30) return RGF_ERR_UNSUPPORTED;
+  if (schedule == RGF_SCHEDULE_LONGEST_FIRST) {
+    std::stable_sort(items.begin(), items.end(), [](const Item& x, const Item& y) { return x.cost > y.cost; });
+  } else if (schedule == RGF_SCHEDULE_INTERLEAVED) {
+    // longest first inside each block size, then take one from each size in turn
+    std::vector<std::vector<Item>> by(4);
+    for (const Item& it : items) by[it.b / 32 - 1].push_back(it);
+    for (auto& v : by)
+      std::stable_sort(v.begin(), v.end(), [](const Item& x, const Item& y) { return x.cost > y.cost; });
+    std::vector<size_t> pos(4, 0);
+    items.clear();
+    for (bool more = true; more;) {
+      more = false;
+      for (int c = 3; c >= 0; --c)
+        if (pos[c] < by[c].size()) {
+          items.push_back(by[c][pos[c]++]);
+          more = true;
+        }
+    }
+  }
+  const int n = (int)items.size();
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return RGF_ERR_HIP;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return RGF_ERR_HIP;
+  const int g = std::max(1, std::min(grid > 0 ? grid : cus, n));
+  std::vector<int> host(3 * (size_t)n);
+  for (int k = 0; k < n; ++k) {
+    host[k] = k;                       // instance id = queue position: the tables are in queue order
+    host[n + k] = items[k].dev;
+    host[2 * n + k] = items[k].en;
+  }
+  rgf_plan_s* p = new (std::nothrow) rgf_plan_s();
+  if (!p) return RGF_ERR_OUT_OF_MEMORY;
+  p->batched = 1;
+  p->d = rgf_desc_t{};
+  p->d.precision = precision;
+  p->shapes.assign(shapes, shapes + num_devices);
+  p->n_items = n;
+  p->grid = g;
+  p->ws_slot = slot;
+  if (hipMalloc(&p->d_index, host.size() * sizeof(int)) != hipSuccess) {
+    delete p;
+    return RGF_ERR_OUT_OF_MEMORY;
+  }
+  if (hipMemcpy(p->d_index, host.data(), host.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
+    hipFree(p->d_index);
+    delete p;
+    return RGF_ERR_HIP;
+  }
+  p->ws_bytes = 256 + (size_t)g * slot * sizeof(double2);
+  *plan = p;
+  if (workspace_bytes) *workspace_bytes = p->ws_bytes;
+  return RGF_OK;
+}
+
+rgf_status_t rgf_batched_solve(rgf_plan_t plan, const rgf_batch_device_t* devices, double eta_d,
+                               void* workspace, size_t workspace_bytes, void* stream) {
+  if (!plan || !plan->batched) return plan ? RGF_ERR_PLAN_MISMATCH : RGF_ERR_INVALID_ARG;
+  if (!devices) return RGF_ERR_INVALID_ARG;
+  if (!workspace || workspace_bytes < plan->ws_bytes) return RGF_ERR_WORKSPACE_TOO_SMALL;
+  char* ws = static_cast<char*>(workspace);
+  rgfk::BatchArgs a{};
+  a.devs = devices;
+  a.queue = plan->d_index;
+  a.inst_dev = plan->d_index + plan->n_items;
+  a.inst_energy = plan->d_index + 2 * (size_t)plan->n_items;
+  a.n_items = plan->n_items;
+  a.counter = reinterpret_cast<int*>(ws);
+  a.ws_slots = reinterpret_cast<double2*>(ws + 256);
+  a.ws_slot = plan->ws_slot;
+  a.eta_d = eta_d;
+  a.mixed = plan->d.precision == RGF_MIXED_FP32 ? 1 : 0;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (st == nullptr) {
+    // the default stream cannot be captured: launch directly
+    return rgfk::launch_rgf_batched(a, plan->grid, st) == hipSuccess ? RGF_OK : RGF_ERR_HIP;
+  }
+  std::lock_guard<std::mutex> lock(plan->mu);
+  const bool same = plan->has_graph && plan->g_devs == devices && plan->g_ws == workspace &&
+                    plan->g_eta == eta_d && plan->g_stream == st;
+  if (!same) {
+    if (plan->has_graph) {
+      hipGraphExecDestroy(plan->exec);
+      hipGraphDestroy(plan->graph);
+      plan->has_graph = false;
+    }
+    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      return rgfk::launch_rgf_batched(a, plan->grid, st) == hipSuccess ? RGF_OK : RGF_ERR_HIP;
+    }
+    hipError_t le = rgfk::launch_rgf_batched(a, plan->grid, st);
+    hipGraph_t graph = nullptr;
+    hipError_t ce = hipStreamEndCapture(st, &graph);
+    if (le != hipSuccess || ce != hipSuccess) {
+      if (graph) hipGraphDestroy(graph);
+      return RGF_ERR_HIP;
+    }
+    hipGraphExec_t exec = nullptr;
+    if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+      hipGraphDestroy(graph);
+      return RGF_ERR_HIP;
+    }
+    plan->graph = graph;
+    plan->exec = exec;
+    plan->has_graph = true;
+    plan->g_devs = devices;
+    plan->g_ws = workspace;
+    plan->g_eta = eta_d;
+    plan->g_stream = st;
+  }
+  return hipGraphLaunch(plan->exec, st) == hipSuccess ? RGF_OK : RGF_ERR_HIP;
 }
 
 rgf_status_t rgf_solve(rgf_plan_t plan, const void* H, const void* sigma_L, const void* sigma_R,
                        const double* energies, double eta_d, void* G, double* T, int32_t* info,
                        void* workspace, size_t workspace_bytes, void* stream) {
   if (!plan) return RGF_ERR_INVALID_ARG;
-  if (plan->d.method != RGF_METHOD_SEQUENTIAL) return RGF_ERR_PLAN_MISMATCH;
+  if (plan->batched || plan->d.method != RGF_METHOD_SEQUENTIAL) return RGF_ERR_PLAN_MISMATCH;
   if (!H || !sigma_L || !sigma_R || !energies || !G || !info) return RGF_ERR_INVALID_ARG;
   if (!workspace || workspace_bytes < plan->ws_bytes) return RGF_ERR_WORKSPACE_TOO_SMALL;
   const rgf_desc_t& d = plan->d;
@@ -168,7 +324,7 @@ rgf_status_t ddrgf_solve(rgf_plan_t plan, const void* H, const void* sigma_L, co
                          const double* energies, double eta_d, void* G, double* T, int32_t* info,
                          void* workspace, size_t workspace_bytes, void* stream) {
   if (!plan) return RGF_ERR_INVALID_ARG;
-  if (plan->d.method != RGF_METHOD_DDRGF) return RGF_ERR_PLAN_MISMATCH;
+  if (plan->batched || plan->d.method != RGF_METHOD_DDRGF) return RGF_ERR_PLAN_MISMATCH;
   if (!H || !sigma_L || !sigma_R || !energies || !G || !info) return RGF_ERR_INVALID_ARG;
   if (!workspace || workspace_bytes < plan->ws_bytes) return RGF_ERR_WORKSPACE_TOO_SMALL;
   const rgf_desc_t& d = plan->d;

@@ -4,6 +4,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "../../include/rgf.h"
+
 namespace rgfk {
 
 // Sequential RGF sweep, block tridiagonal (w = 1), one workgroup per chain.
@@ -63,6 +65,22 @@ struct DDArgs {
 size_t ddrgf_interior_ws_elems(int nmax, int bp);
 void ddrgf_layout_host(int l, int m, int* base, int* rem);
 hipError_t launch_ddrgf(const DDArgs& a, hipStream_t s);
+
+// Persistent batched launch (see rgf_batched_kernel).
+struct BatchArgs {
+  const rgf_batch_device_t* devs;   // device table [n_dev]
+  const int* queue;                 // [n_items] instance ids in processing order
+  const int* inst_dev;              // [n_items] device of each instance
+  const int* inst_energy;           // [n_items] energy index of each instance
+  int n_items;
+  int* counter;                     // work-queue counter (reset by the launch)
+  double2* ws_slots;                // one slot per persistent workgroup
+  size_t ws_slot;                   // elements per slot
+  double eta_d;
+  int mixed;
+};
+
+hipError_t launch_rgf_batched(const BatchArgs& a, int grid, hipStream_t s);
 
 // Native n-diagonal sweep (w >= 1), one workgroup per energy.
 struct NSweepArgs {

@@ -1,7 +1,7 @@
 // Sequential RGF for block tridiagonal systems (paper Sec. 2.2, Algorithm 1) on gfx950.
 //
-// One workgroup (4 wave64) per chain; the chain's layer loop runs inside the kernel
-// so the host boundary is crossed once.  Per layer:
+// One workgroup per chain (one system at one energy); the chain's layer loop runs
+// inside the kernel so the host boundary is crossed once.  Per layer:
 //   upward   g_i = S_i^{-1}  (register-resident blocked Gauss-Jordan)
 //            L_i = g_i M_{i,i-1},  U_i = M_{i-1,i} g_i,
 //            S_{i-1} = M_{i-1,i-1} - M_{i-1,i} L_i   (assembled from H, E, Sigma on the fly)
@@ -9,6 +9,11 @@
 //            G_ii = g_i - L_i G_{i-1,i},  first block row R_i = -R_{i-1} U_i (R_0 = G_00)
 // and finally T = Re Tr[Gamma_L R_{l-1} Gamma_R R_{l-1}^H], Gamma = i (Sigma - Sigma^H).
 // g_i, U_i, L_i are kept in the workspace between the two passes.
+//
+// Two kernels share the per-chain body rgf_chain():
+//   rgf_sweep_kernel    one workgroup per chain of a uniform batch (all outputs);
+//   rgf_batched_kernel  persistent: workgroups pull chains of uneven size from a
+//                       work queue (longest first) and write T and the diagonal blocks.
 #include "block_engine.h"
 #include "kernels.h"
 
@@ -17,52 +22,60 @@ namespace rgfk {
 int padded_block(int b) { return ((b + 15) / 16) * 16; }
 
 size_t sweep_ws_chain_elems(int l, int bp) {
-  // g[l], U[l], L[l], R[2], Gamma_L, Gamma_R, X1, and two blocks for the pivot refinement
-  return (size_t)(3 * (size_t)l + 7) * (size_t)bp * (size_t)bp;
+  // g[l], U[l], L[l], R[2], Gamma_L, Gamma_R, X1, two blocks for the pivot refinement,
+  // and one for G_{i-1,i} when the off-diagonal output is not wanted
+  return (size_t)(3 * (size_t)l + 8) * (size_t)bp * (size_t)bp;
 }
 
+// Everything one chain needs.  Off-diagonal outputs Gl/Gu may be null (then not
+// written; G_{i-1,i} goes to workspace scratch), first_row may be null, T may be null.
+struct Chain {
+  const double2* Hl;   // block (i, i-1) at Hl + i bb
+  const double2* Hd;   // block (i, i)
+  const double2* Hu;   // block (i, i+1)
+  const double2* sL;   // null in direct mode
+  const double2* sR;
+  double2 z;           // E + i eta_d
+  int direct;
+  double2* Gl;
+  double2* Gd;         // diagonal blocks (always written)
+  double2* Gu;
+  double2* first_row;
+  double* T;
+  int* info;
+  double2* ws;
+  int l, b;
+};
+
 template <int T, int NW, int MIXED>
-__global__ __launch_bounds__(64 * NW, 1) void rgf_sweep_kernel(SweepArgs a) {
+__device__ __forceinline__ void rgf_chain(const Chain& ch, GJShared& sh, double* red) {
   constexpr int BP = 16 * T;
   constexpr int NT = 64 * NW;
-  __shared__ GJShared sh;
-  __shared__ double red[NW];
-
-  const int e = blockIdx.x;
   const int t = threadIdx.x;
-  const int l = a.l, b = a.b;
+  const int l = ch.l, b = ch.b;
   const size_t bb = (size_t)b * b, bpbp = (size_t)BP * BP;
-  double2* ws = a.ws + (size_t)e * a.ws_chain;
-  double2* g = ws;
-  double2* U = ws + (size_t)l * bpbp;
-  double2* L = ws + (size_t)2 * l * bpbp;
-  double2* Rb = ws + (size_t)3 * l * bpbp;
+  double2* g = ch.ws;
+  double2* U = g + (size_t)l * bpbp;
+  double2* L = g + (size_t)2 * l * bpbp;
+  double2* Rb = g + (size_t)3 * l * bpbp;
   double2* GamL = Rb + 2 * bpbp;
   double2* GamR = GamL + bpbp;
   double2* X1 = GamR + bpbp;
   double2* Ssave = X1 + bpbp;     // pivot before inversion (refinement)
   double2* Rres = Ssave + bpbp;   // I - S g (refinement)
-
-  const double2* H = a.H + (size_t)e * a.h_stride;
-  const double2* Hl = H;                          // block (i, i-1) at Hl + i*bb
-  const double2* Hd = H + (size_t)l * bb;         // block (i, i)
-  const double2* Hu = H + (size_t)2 * l * bb;     // block (i, i+1)
-  const double2* sL = a.direct ? nullptr : a.sigL + (size_t)e * bb;
-  const double2* sR = a.direct ? nullptr : a.sigR + (size_t)e * bb;
-  const double2 z = make_double2(a.direct ? 0.0 : a.E[e], a.direct ? 0.0 : a.eta_d);
+  double2* Gup = Rres + bpbp;     // G_{i-1,i} when Gu is not an output
   // off-diagonal blocks of M are -H (assembled) or the stored band (direct)
-  const double ms = a.direct ? 1.0 : -1.0;
-  double2* Gout = a.G + (size_t)e * a.g_stride;
-  double2* Gl = Gout;
-  double2* Gd = Gout + (size_t)l * bb;
-  double2* Gu = Gout + (size_t)2 * l * bb;
+  const double ms = ch.direct ? 1.0 : -1.0;
+  const double2* Hl = ch.Hl;
+  const double2* Hd = ch.Hd;
+  const double2* Hu = ch.Hu;
 
   int bad_layer = -1;
   Acc<T, NW> acc;
 
   // acc (+)= M_ii: assembled from H, E, Sigma, or read from the direct band
-  auto diag = [&](int i, bool add) {
-    if (a.direct) {
+  auto diag = [&](int i) {
+    if (ch.direct) {
       add_from<T, NW>(acc, opnd(Hd + (size_t)i * bb, b, b, b));
       // identity on the padding of a directly given block
       const int ln = lane_id();
@@ -78,8 +91,8 @@ __global__ __launch_bounds__(64 * NW, 1) void rgf_sweep_kernel(SweepArgs a) {
             if (ii == jj && ii >= b && tr0 + r < T && tc0 + c < T) acc.re[r][c][v] += 1.0;
           }
     } else {
-      assemble_diag<T, NW>(acc, Hd + (size_t)i * bb, b, z, i == 0 ? sL : nullptr,
-                           i == l - 1 ? sR : nullptr, add);
+      assemble_diag<T, NW>(acc, Hd + (size_t)i * bb, b, ch.z, i == 0 ? ch.sL : nullptr,
+                           i == l - 1 ? ch.sR : nullptr, true);
     }
   };
   auto P = [&](const double2* p) { return opnd(p, BP, BP, BP); };
@@ -87,7 +100,7 @@ __global__ __launch_bounds__(64 * NW, 1) void rgf_sweep_kernel(SweepArgs a) {
 
   // ---------------- upward pass ----------------
   acc_zero<T, NW>(acc);
-  diag(l - 1, true);
+  diag(l - 1);
   for (int i = l - 1; i >= 0; --i) {
     double2* gi = g + (size_t)i * bpbp;
     if (MIXED) store<T, NW>(acc, Ssave, BP, BP, BP);
@@ -115,51 +128,89 @@ __global__ __launch_bounds__(64 * NW, 1) void rgf_sweep_kernel(SweepArgs a) {
     __syncthreads();
     // S_{i-1} = M_{i-1,i-1} - M_{i-1,i} L_i
     gemm_to<MIXED, T, NW>(acc, Pb(Hu + (size_t)(i - 1) * bb), P(L + (size_t)i * bpbp), -ms);
-    diag(i - 1, true);
+    diag(i - 1);
   }
 
   // ---------------- downward pass ----------------
   load<T, NW>(acc, P(g));
-  store<T, NW>(acc, Gd, b, b, b);
+  store<T, NW>(acc, ch.Gd, b, b, b);
   store<T, NW>(acc, Rb, BP, BP, BP);
-  if (a.first_row) store<T, NW>(acc, a.first_row + (size_t)e * l * bb, b, b, b);
+  if (ch.first_row) store<T, NW>(acc, ch.first_row, b, b, b);
   __syncthreads();
   for (int i = 1; i < l; ++i) {
-    const double2* Gp = Gd + (size_t)(i - 1) * bb;
+    const double2* Gp = ch.Gd + (size_t)(i - 1) * bb;
     const double2* Ui = U + (size_t)i * bpbp;
     const double2* Li = L + (size_t)i * bpbp;
+    // G_{i-1,i}: to the output band, or to scratch when only the diagonal is wanted
+    double2* Gup_i = ch.Gu ? ch.Gu + (size_t)(i - 1) * bb : Gup;
     gemm_to<MIXED, T, NW>(acc, Pb(Gp), P(Ui), -1.0);
-    store<T, NW>(acc, Gu + (size_t)(i - 1) * bb, b, b, b);
-    gemm_to<MIXED, T, NW>(acc, P(Li), Pb(Gp), -1.0);
-    store<T, NW>(acc, Gl + (size_t)i * bb, b, b, b);
-    gemm_to<MIXED, T, NW>(acc, P(Rb + (size_t)((i - 1) & 1) * bpbp), P(Ui), -1.0);
-    store<T, NW>(acc, Rb + (size_t)(i & 1) * bpbp, BP, BP, BP);
-    if (a.first_row) store<T, NW>(acc, a.first_row + ((size_t)e * l + i) * bb, b, b, b);
+    store<T, NW>(acc, Gup_i, b, b, b);
+    if (ch.Gl) {
+      gemm_to<MIXED, T, NW>(acc, P(Li), Pb(Gp), -1.0);
+      store<T, NW>(acc, ch.Gl + (size_t)i * bb, b, b, b);
+    }
+    if (ch.T || ch.first_row) {
+      gemm_to<MIXED, T, NW>(acc, P(Rb + (size_t)((i - 1) & 1) * bpbp), P(Ui), -1.0);
+      store<T, NW>(acc, Rb + (size_t)(i & 1) * bpbp, BP, BP, BP);
+      if (ch.first_row) store<T, NW>(acc, ch.first_row + (size_t)i * bb, b, b, b);
+    }
     __syncthreads();
-    gemm_to<MIXED, T, NW>(acc, P(Li), Pb(Gu + (size_t)(i - 1) * bb), -1.0);
+    gemm_to<MIXED, T, NW>(acc, P(Li), Pb(Gup_i), -1.0);
     add_from<T, NW>(acc, P(g + (size_t)i * bpbp));
-    store<T, NW>(acc, Gd + (size_t)i * bb, b, b, b);
+    store<T, NW>(acc, ch.Gd + (size_t)i * bb, b, b, b);
     __syncthreads();
   }
 
   // ---------------- transmission ----------------
   double Tval = 0.0;
-  if (a.T && !a.direct)
-    Tval = transmission<T, NW>(acc, Rb + (size_t)((l - 1) & 1) * bpbp, sL, sR, b, GamL, GamR, X1, red);
+  if (ch.T && !ch.direct)
+    Tval = transmission<T, NW>(acc, Rb + (size_t)((l - 1) & 1) * bpbp, ch.sL, ch.sR, b, GamL, GamR, X1, red);
 
   // ---------------- status ----------------
   if (bad_layer >= 0) {
     const double qnan = __builtin_nan("");
-    for (size_t idx = t; idx < (size_t)3 * l * bb; idx += NT) Gout[idx] = make_double2(qnan, qnan);
-    if (a.first_row)
-      for (size_t idx = t; idx < (size_t)l * bb; idx += NT)
-        a.first_row[(size_t)e * l * bb + idx] = make_double2(qnan, qnan);
+    for (size_t idx = t; idx < (size_t)l * bb; idx += NT) {
+      ch.Gd[idx] = make_double2(qnan, qnan);
+      if (ch.Gl) ch.Gl[idx] = make_double2(qnan, qnan);
+      if (ch.Gu) ch.Gu[idx] = make_double2(qnan, qnan);
+      if (ch.first_row) ch.first_row[idx] = make_double2(qnan, qnan);
+    }
     Tval = qnan;
   }
   if (t == 0) {
-    if (a.T && !a.direct) a.T[e] = Tval;
-    if (a.info) a.info[(size_t)e * a.info_stride + a.info_offset] = bad_layer >= 0 ? bad_layer + 1 : 0;
+    if (ch.T && !ch.direct) *ch.T = Tval;
+    if (ch.info) *ch.info = bad_layer >= 0 ? bad_layer + 1 : 0;
   }
+  __syncthreads();
+}
+
+template <int T, int NW, int MIXED>
+__global__ __launch_bounds__(64 * NW, 1) void rgf_sweep_kernel(SweepArgs a) {
+  __shared__ GJShared sh;
+  __shared__ double red[NW];
+  const int e = blockIdx.x;
+  const int l = a.l, b = a.b;
+  const size_t bb = (size_t)b * b;
+  const double2* H = a.H + (size_t)e * a.h_stride;
+  Chain ch;
+  ch.Hl = H;
+  ch.Hd = H + (size_t)l * bb;
+  ch.Hu = H + (size_t)2 * l * bb;
+  ch.direct = a.direct;
+  ch.sL = a.direct ? nullptr : a.sigL + (size_t)e * bb;
+  ch.sR = a.direct ? nullptr : a.sigR + (size_t)e * bb;
+  ch.z = make_double2(a.direct ? 0.0 : a.E[e], a.direct ? 0.0 : a.eta_d);
+  double2* Gout = a.G + (size_t)e * a.g_stride;
+  ch.Gl = Gout;
+  ch.Gd = Gout + (size_t)l * bb;
+  ch.Gu = Gout + (size_t)2 * l * bb;
+  ch.first_row = a.first_row ? a.first_row + (size_t)e * l * bb : nullptr;
+  ch.T = (a.T && !a.direct) ? a.T + e : nullptr;
+  ch.info = a.info ? a.info + (size_t)e * a.info_stride + a.info_offset : nullptr;
+  ch.ws = a.ws + (size_t)e * a.ws_chain;
+  ch.l = l;
+  ch.b = b;
+  rgf_chain<T, NW, MIXED>(ch, sh, red);
 }
 
 template <int T>
@@ -185,6 +236,77 @@ hipError_t launch_rgf_sweep(const SweepArgs& a, hipStream_t s) {
     case 8: return launch_T<8>(a, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+// ---------------------------------------------------------------------------
+// Persistent batched launch over instances of uneven size.
+//
+// An instance is one (device, energy) pair; device d has its own band H_d (l_d layers
+// of b_d orbitals, b_d a multiple of 16 up to 128) and its own energies.  The plan
+// sorts the instances into queue[] (longest first by default); every workgroup takes
+// the next queue entry with one atomic increment of a counter in the workspace, runs
+// the whole chain with the code path of its block size, and stops when the queue is
+// empty (every workgroup reaches that test, so the grid always drains).  Each
+// workgroup owns one workspace slot sized for the largest chain.
+// ---------------------------------------------------------------------------
+template <int MIXED>
+__global__ __launch_bounds__(512, 1) void rgf_batched_kernel(BatchArgs a) {
+  __shared__ GJShared sh;
+  __shared__ double red[8];
+  __shared__ int s_item;
+  double2* ws = a.ws_slots + (size_t)blockIdx.x * a.ws_slot;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(a.counter, 1);
+    __syncthreads();
+    const int item = s_item;
+    __syncthreads();
+    if (item >= a.n_items) break;
+    const int inst = a.queue[item];
+    const int d = a.inst_dev[inst], e = a.inst_energy[inst];
+    const rgf_batch_device_t dv = a.devs[d];
+    const int l = dv.num_layers, b = dv.block_size;
+    const size_t bb = (size_t)b * b;
+    const double2* H = static_cast<const double2*>(dv.H);
+    Chain ch;
+    ch.Hl = H;
+    ch.Hd = H + (size_t)l * bb;
+    ch.Hu = H + (size_t)2 * l * bb;
+    ch.direct = 0;
+    ch.sL = static_cast<const double2*>(dv.sigma_L) + (size_t)e * bb;
+    ch.sR = static_cast<const double2*>(dv.sigma_R) + (size_t)e * bb;
+    ch.z = make_double2(dv.energies[e], a.eta_d);
+    ch.Gl = nullptr;
+    ch.Gu = nullptr;
+    ch.Gd = static_cast<double2*>(dv.G_diag) + (size_t)e * l * bb;
+    ch.first_row = nullptr;
+    ch.T = dv.T ? dv.T + e : nullptr;
+    ch.info = dv.info + e;
+    ch.ws = ws;
+    ch.l = l;
+    ch.b = b;
+    switch (b >> 4) {
+      case 2: rgf_chain<2, 8, MIXED>(ch, sh, red); break;
+      case 4: rgf_chain<4, 8, MIXED>(ch, sh, red); break;
+      case 6: rgf_chain<6, 8, MIXED>(ch, sh, red); break;
+      case 8: rgf_chain<8, 8, MIXED>(ch, sh, red); break;
+      default: break;   // rejected at plan creation
+    }
+  }
+}
+
+__global__ void reset_counter_kernel(int* counter) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) counter[0] = 0;
+}
+
+hipError_t launch_rgf_batched(const BatchArgs& a, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, s, a.counter);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  if (a.mixed)
+    hipLaunchKernelGGL((rgf_batched_kernel<1>), dim3(grid), dim3(512), 0, s, a);
+  else
+    hipLaunchKernelGGL((rgf_batched_kernel<0>), dim3(grid), dim3(512), 0, s, a);
+  return hipGetLastError();
 }
 
 }  // namespace rgfk

@@ -31,7 +31,8 @@ def declared_symbols():
 
 def test_header_declares_entry_points():
     syms = declared_symbols()
-    for s in ("rgf_plan_create", "rgf_plan_destroy", "rgf_solve", "ddrgf_solve"):
+    for s in ("rgf_plan_create", "rgf_plan_destroy", "rgf_solve", "ddrgf_solve", "rgf_batched_plan_create",
+              "rgf_batched_solve"):
         assert s in syms
 
 
@@ -54,7 +55,7 @@ def test_plan_workspace_size(l, b, w, ne):
     binding = _lib()
     p = binding.Plan(l, b, w, ne)
     bp = ((b + 15) // 16) * 16
-    assert p.workspace_bytes == (3 * l + 7) * bp * bp * 16 * ne
+    assert p.workspace_bytes == (3 * l + 8) * bp * bp * 16 * ne
     p.close()
 
 
