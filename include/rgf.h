@@ -84,8 +84,8 @@ typedef struct {
   int64_t num_domains;       /* DDRGF: number of (interior, separator) pairs m >= 1 */
   int64_t separator_layers;  /* DDRGF: layers per separator; 0 means w (the only value supported) */
   int32_t want_transmission; /* nonzero: T is computed when the T pointer is not NULL */
-  int32_t reserved0;
-  int64_t reserved1;
+  int32_t want_backward;     /* nonzero: rgf_solve keeps what rgf_backward needs (sequential, w = 1, FP64) */
+  int64_t checkpoint_domains;/* rgf_backward: layers are cut into this many domains (0 = 8) */
 } rgf_desc_t;
 
 /* Validate a description and build a plan.  *workspace_bytes receives the size of
@@ -165,6 +165,23 @@ rgf_status_t rgf_batched_plan_create(int64_t num_devices, const rgf_batch_shape_
  * info[].  Calls on one plan from several host threads are serialised. */
 rgf_status_t rgf_batched_solve(rgf_plan_t plan, const rgf_batch_device_t* devices, double eta_d,
                                void* workspace, size_t workspace_bytes, void* stream);
+
+/* Adjoint of the transmission with respect to on-site energies.
+ *
+ * For L = sum_E dL_dT[E] T(E) and on-site shifts eps (H_ii,ss += eps_{i,s}, so
+ * M_ss -= eps), first-order perturbation dG = G dH G gives
+ *     dT/d eps_{i,s} = 2 Re[(G_{i,l-1} X G_{0,i})_{ss}],  X = Gamma_R G_{0,l-1}^H Gamma_L.
+ * The plan must have been created with want_backward (sequential method, w = 1,
+ * FP64) and rgf_solve must have run with it on the same inputs, G and workspace
+ * (left untouched in between): the forward stored the sweep blocks U_i and, at the
+ * boundaries of checkpoint_domains domains, the first block row G_{0,i} and the
+ * last-column propagator P_i = -U_{i+1} P_{i+1}; the adjoint runs one workgroup
+ * per (energy, domain), recomputes both inside its domain from the checkpoints,
+ * and writes d_onsite[l][b] (device, real) = sum over energies in a fixed order
+ * (deterministic).  dL_dT: [nE] device doubles. */
+rgf_status_t rgf_backward(rgf_plan_t plan, const void* sigma_L, const void* sigma_R, const void* G,
+                          const double* dL_dT, double* d_onsite, void* workspace, size_t workspace_bytes,
+                          void* stream);
 
 /* Static text of a status code. */
 const char* rgf_status_string(rgf_status_t status);

@@ -32,8 +32,8 @@ class RgfDesc(ctypes.Structure):
         ("num_domains", ctypes.c_int64),
         ("separator_layers", ctypes.c_int64),
         ("want_transmission", ctypes.c_int32),
-        ("reserved0", ctypes.c_int32),
-        ("reserved1", ctypes.c_int64),
+        ("want_backward", ctypes.c_int32),
+        ("checkpoint_domains", ctypes.c_int64),
     ]
 
 
@@ -84,6 +84,8 @@ def load() -> ctypes.CDLL:
     lib.rgf_batched_plan_create.restype = ctypes.c_int
     lib.rgf_batched_solve.argtypes = [_VP, _VP, ctypes.c_double, _VP, ctypes.c_size_t, _VP]
     lib.rgf_batched_solve.restype = ctypes.c_int
+    lib.rgf_backward.argtypes = [_VP, _VP, _VP, _VP, _VP, _VP, _VP, ctypes.c_size_t, _VP]
+    lib.rgf_backward.restype = ctypes.c_int
     lib.rgf_status_string.argtypes = [ctypes.c_int]
     lib.rgf_status_string.restype = ctypes.c_char_p
     lib.rgf_version.argtypes = []
@@ -96,10 +98,12 @@ class Plan:
     """Owning wrapper of an rgf_plan_t."""
 
     def __init__(self, l: int, b: int, w: int, ne: int, method: str = "rgf", precision: str = "fp64",
-                 domains: int = 0, separator_layers: int = 0, want_transmission: bool = True):
+                 domains: int = 0, separator_layers: int = 0, want_transmission: bool = True,
+                 want_backward: bool = False, checkpoint_domains: int = 0):
         self.lib = load()
         self.desc = RgfDesc(l, b, w, ne, PRECISION[precision], METHOD[method], domains,
-                            separator_layers, 1 if want_transmission else 0, 0, 0)
+                            separator_layers, 1 if want_transmission else 0, 1 if want_backward else 0,
+                            checkpoint_domains)
         self.handle = _VP()
         ws = ctypes.c_size_t(0)
         st = self.lib.rgf_plan_create(ctypes.byref(self.desc), ctypes.byref(self.handle), ctypes.byref(ws))
@@ -133,6 +137,13 @@ def rgf_solve(plan: Plan, H, sigma_L, sigma_R, energies, eta_d: float, G, T, inf
                             stream)
     if st != RGF_OK:
         raise RgfError("rgf_solve", st)
+
+
+def rgf_backward(plan: Plan, sigma_L, sigma_R, G, dL_dT, d_onsite, workspace, stream: int = 0) -> None:
+    st = plan.lib.rgf_backward(plan.handle, _ptr(sigma_L), _ptr(sigma_R), _ptr(G), _ptr(dL_dT), _ptr(d_onsite),
+                               _ptr(workspace), workspace.numel() * workspace.element_size(), stream)
+    if st != RGF_OK:
+        raise RgfError("rgf_backward", st)
 
 
 def ddrgf_solve(plan: Plan, H, sigma_L, sigma_R, energies, eta_d: float, G, T, info, workspace,

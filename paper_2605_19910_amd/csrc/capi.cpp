@@ -14,6 +14,9 @@ struct rgf_plan_s {
   int bp;
   size_t ws_bytes;
   size_t ws_chain;   // sequential sweep: workspace elements per energy
+  // adjoint (want_backward): checkpoint domains, scratch and per-energy gradients
+  int nd = 0, dlen = 0;
+  size_t off_adj = 0, adj_chain = 0, off_grad = 0;
   // DDRGF workspace layout (byte offsets)
   size_t dd_int_chain, dd_red_chain;
   size_t off_int, off_ms, off_gs, off_gsrow, off_red, off_fin, off_info;
@@ -56,6 +59,11 @@ rgf_status_t validate(const rgf_desc_t* d) {
     return RGF_ERR_UNSUPPORTED;
   if (d->method != RGF_METHOD_SEQUENTIAL && d->method != RGF_METHOD_DDRGF) return RGF_ERR_INVALID_ARG;
   if (d->half_bandwidth > 4) return RGF_ERR_UNSUPPORTED;
+  if (d->want_backward) {
+    if (d->method != RGF_METHOD_SEQUENTIAL || d->half_bandwidth != 1 || d->precision != RGF_FP64)
+      return RGF_ERR_UNSUPPORTED;
+    if (d->checkpoint_domains < 0) return RGF_ERR_INVALID_ARG;
+  }
   if (d->method == RGF_METHOD_DDRGF) {
     const int64_t w = d->half_bandwidth;
     const int64_t s1 = d->separator_layers == 0 ? w : d->separator_layers;
@@ -91,6 +99,18 @@ rgf_status_t rgf_plan_create(const rgf_desc_t* desc, rgf_plan_t* plan, size_t* w
   else
     p->ws_chain = rgfk::nrgf_ws_chain_elems((int)desc->num_layers, w, p->bp);
   p->ws_bytes = p->ws_chain * sizeof(double2) * (size_t)desc->num_energies;
+  if (desc->want_backward) {
+    const int l = (int)desc->num_layers, ne = (int)desc->num_energies;
+    const size_t bpbp = (size_t)p->bp * p->bp;
+    const int req = desc->checkpoint_domains > 0 ? (int)std::min<int64_t>(desc->checkpoint_domains, l) : std::min(8, l);
+    p->dlen = (l + req - 1) / req;
+    p->nd = (l + p->dlen - 1) / p->dlen;
+    p->ws_chain += (size_t)(2 * p->nd + 1) * bpbp;
+    p->adj_chain = (size_t)(p->dlen + 7) * bpbp;
+    p->off_adj = align256(p->ws_chain * sizeof(double2) * (size_t)ne);
+    p->off_grad = align256(p->off_adj + p->adj_chain * sizeof(double2) * (size_t)ne * p->nd);
+    p->ws_bytes = align256(p->off_grad + (size_t)ne * l * desc->block_size * sizeof(double));
+  }
   if (desc->method == RGF_METHOD_DDRGF) {
     const int l = (int)desc->num_layers / w, m = (int)desc->num_domains, ne = (int)desc->num_energies;
     const size_t b = (size_t)desc->block_size * w, bb = b * b;
@@ -316,6 +336,8 @@ rgf_status_t rgf_solve(rgf_plan_t plan, const void* H, const void* sigma_L, cons
   a.b = (int)d.block_size;
   a.chains = (int)d.num_energies;
   a.mixed = d.precision == RGF_MIXED_FP32 ? 1 : 0;
+  a.nd = d.want_backward ? plan->nd : 0;
+  a.dlen = d.want_backward ? plan->dlen : 0;
   hipError_t e = rgfk::launch_rgf_sweep(a, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? RGF_OK : RGF_ERR_HIP;
 }
@@ -374,6 +396,34 @@ rgf_status_t ddrgf_solve(rgf_plan_t plan, const void* H, const void* sigma_L, co
   a.mixed = d.precision == RGF_MIXED_FP32 ? 1 : 0;
   hipError_t e = rgfk::launch_ddrgf(a, st);
   if (e == hipSuccess && w > 1) e = rgfk::launch_unfuse(f, st);
+  return e == hipSuccess ? RGF_OK : RGF_ERR_HIP;
+}
+
+rgf_status_t rgf_backward(rgf_plan_t plan, const void* sigma_L, const void* sigma_R, const void* G,
+                          const double* dL_dT, double* d_onsite, void* workspace, size_t workspace_bytes,
+                          void* stream) {
+  if (!plan) return RGF_ERR_INVALID_ARG;
+  if (plan->batched || !plan->d.want_backward) return RGF_ERR_PLAN_MISMATCH;
+  if (!sigma_L || !sigma_R || !G || !dL_dT || !d_onsite) return RGF_ERR_INVALID_ARG;
+  if (!workspace || workspace_bytes < plan->ws_bytes) return RGF_ERR_WORKSPACE_TOO_SMALL;
+  char* ws = static_cast<char*>(workspace);
+  rgfk::AdjArgs a{};
+  a.sigL = static_cast<const double2*>(sigma_L);
+  a.sigR = static_cast<const double2*>(sigma_R);
+  a.G = static_cast<const double2*>(G);
+  a.dLdT = dL_dT;
+  a.gradE = reinterpret_cast<double*>(ws + plan->off_grad);
+  a.d_onsite = d_onsite;
+  a.ws = reinterpret_cast<double2*>(ws);
+  a.ws_chain = plan->ws_chain;
+  a.scratch = reinterpret_cast<double2*>(ws + plan->off_adj);
+  a.scratch_chain = plan->adj_chain;
+  a.l = (int)plan->d.num_layers;
+  a.b = (int)plan->d.block_size;
+  a.ne = (int)plan->d.num_energies;
+  a.nd = plan->nd;
+  a.dlen = plan->dlen;
+  hipError_t e = rgfk::launch_rgf_adjoint(a, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? RGF_OK : RGF_ERR_HIP;
 }
 

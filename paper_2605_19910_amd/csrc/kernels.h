@@ -33,9 +33,31 @@ struct SweepArgs {
   size_t ws_chain;
   int l, b, chains;
   int mixed;                 // 1: products on FP32 MFMA, FP64 pivots + one refinement step
+  int nd, dlen;              // adjoint checkpoints: nd domains of dlen layers (nd = 0: none);
+                             // stored after the sweep state of each chain's workspace
 };
 
-size_t sweep_ws_chain_elems(int l, int bp);
+// Adjoint of T with respect to on-site energies (one workgroup per (energy, domain)).
+struct AdjArgs {
+  const double2* sigL;       // [ne][b][b]
+  const double2* sigR;
+  const double2* G;          // forward output band [ne][3][l][b][b]
+  const double* dLdT;        // [ne]
+  double* gradE;             // [ne][l][b] per-energy contributions
+  double* d_onsite;          // [l][b] their sum over energies
+  double2* ws;               // forward workspace: chains of ws_chain elements
+  size_t ws_chain;
+  double2* scratch;          // [ne][nd] blocks of scratch_chain elements
+  size_t scratch_chain;
+  int l, b, ne, nd, dlen;
+};
+
+hipError_t launch_rgf_adjoint(const AdjArgs& a, hipStream_t s);
+// g[l], U[l], L[l], R[2], Gamma_L, Gamma_R, X1, two blocks for the pivot refinement,
+// one for G_{i-1,i} when the off-diagonal output is not wanted, two for P
+__host__ __device__ inline size_t sweep_ws_chain_elems(int l, int bp) {
+  return (size_t)(3 * (size_t)l + 10) * (size_t)bp * (size_t)bp;
+}
 int padded_block(int b);
 hipError_t launch_rgf_sweep(const SweepArgs& a, hipStream_t s);
 

@@ -21,11 +21,6 @@ namespace rgfk {
 
 int padded_block(int b) { return ((b + 15) / 16) * 16; }
 
-size_t sweep_ws_chain_elems(int l, int bp) {
-  // g[l], U[l], L[l], R[2], Gamma_L, Gamma_R, X1, two blocks for the pivot refinement,
-  // and one for G_{i-1,i} when the off-diagonal output is not wanted
-  return (size_t)(3 * (size_t)l + 8) * (size_t)bp * (size_t)bp;
-}
 
 // Everything one chain needs.  Off-diagonal outputs Gl/Gu may be null (then not
 // written; G_{i-1,i} goes to workspace scratch), first_row may be null, T may be null.
@@ -45,6 +40,13 @@ struct Chain {
   int* info;
   double2* ws;
   int l, b;
+  // adjoint checkpoints (null = none): P at the last layer of each of nd domains of
+  // dlen layers, the first block row R = G_{0,i} at the first layer of each domain,
+  // and R at the last layer
+  double2* ckP;
+  double2* ckR;
+  double2* Rlast;
+  int nd, dlen;
 };
 
 template <int T, int NW, int MIXED>
@@ -64,6 +66,7 @@ __device__ __forceinline__ void rgf_chain(const Chain& ch, GJShared& sh, double*
   double2* Ssave = X1 + bpbp;     // pivot before inversion (refinement)
   double2* Rres = Ssave + bpbp;   // I - S g (refinement)
   double2* Gup = Rres + bpbp;     // G_{i-1,i} when Gu is not an output
+  double2* Pb = Gup + bpbp;       // 2 blocks: last-column propagator P (adjoint checkpoints)
   // off-diagonal blocks of M are -H (assembled) or the stored band (direct)
   const double ms = ch.direct ? 1.0 : -1.0;
   const double2* Hl = ch.Hl;
@@ -96,9 +99,17 @@ __device__ __forceinline__ void rgf_chain(const Chain& ch, GJShared& sh, double*
     }
   };
   auto P = [&](const double2* p) { return opnd(p, BP, BP, BP); };
-  auto Pb = [&](const double2* p) { return opnd(p, b, b, b); };
+  auto Pn = [&](const double2* p) { return opnd(p, b, b, b); };
+  auto is_last_of_domain = [&](int i) { return i == l - 1 || (i + 1) % ch.dlen == 0; };
 
   // ---------------- upward pass ----------------
+  if (ch.ckP) {
+    // P_{l-1} = I
+    acc_zero<T, NW>(acc);
+    add_identity<T, NW>(acc);
+    store<T, NW>(acc, Pb + (size_t)((l - 1) & 1) * bpbp, BP, BP, BP);
+    store<T, NW>(acc, ch.ckP + (size_t)((l - 1) / ch.dlen) * bpbp, BP, BP, BP);
+  }
   acc_zero<T, NW>(acc);
   diag(l - 1);
   for (int i = l - 1; i >= 0; --i) {
@@ -121,13 +132,20 @@ __device__ __forceinline__ void rgf_chain(const Chain& ch, GJShared& sh, double*
       __syncthreads();
     }
     if (i == 0) break;
-    gemm_to<MIXED, T, NW>(acc, P(gi), Pb(Hl + (size_t)i * bb), ms);
+    gemm_to<MIXED, T, NW>(acc, P(gi), Pn(Hl + (size_t)i * bb), ms);
     store<T, NW>(acc, L + (size_t)i * bpbp, BP, BP, BP);
-    gemm_to<MIXED, T, NW>(acc, Pb(Hu + (size_t)(i - 1) * bb), P(gi), ms);
+    gemm_to<MIXED, T, NW>(acc, Pn(Hu + (size_t)(i - 1) * bb), P(gi), ms);
     store<T, NW>(acc, U + (size_t)i * bpbp, BP, BP, BP);
     __syncthreads();
+    if (ch.ckP) {
+      // P_{i-1} = -U_i P_i; kept at the last layer of every domain
+      gemm_to<MIXED, T, NW>(acc, P(U + (size_t)i * bpbp), P(Pb + (size_t)(i & 1) * bpbp), -1.0);
+      store<T, NW>(acc, Pb + (size_t)((i - 1) & 1) * bpbp, BP, BP, BP);
+      if (is_last_of_domain(i - 1))
+        store<T, NW>(acc, ch.ckP + (size_t)((i - 1) / ch.dlen) * bpbp, BP, BP, BP);
+    }
     // S_{i-1} = M_{i-1,i-1} - M_{i-1,i} L_i
-    gemm_to<MIXED, T, NW>(acc, Pb(Hu + (size_t)(i - 1) * bb), P(L + (size_t)i * bpbp), -ms);
+    gemm_to<MIXED, T, NW>(acc, Pn(Hu + (size_t)(i - 1) * bb), P(L + (size_t)i * bpbp), -ms);
     diag(i - 1);
   }
 
@@ -136,6 +154,8 @@ __device__ __forceinline__ void rgf_chain(const Chain& ch, GJShared& sh, double*
   store<T, NW>(acc, ch.Gd, b, b, b);
   store<T, NW>(acc, Rb, BP, BP, BP);
   if (ch.first_row) store<T, NW>(acc, ch.first_row, b, b, b);
+  if (ch.ckR) store<T, NW>(acc, ch.ckR, BP, BP, BP);
+  if (ch.Rlast && l == 1) store<T, NW>(acc, ch.Rlast, BP, BP, BP);
   __syncthreads();
   for (int i = 1; i < l; ++i) {
     const double2* Gp = ch.Gd + (size_t)(i - 1) * bb;
@@ -143,19 +163,21 @@ __device__ __forceinline__ void rgf_chain(const Chain& ch, GJShared& sh, double*
     const double2* Li = L + (size_t)i * bpbp;
     // G_{i-1,i}: to the output band, or to scratch when only the diagonal is wanted
     double2* Gup_i = ch.Gu ? ch.Gu + (size_t)(i - 1) * bb : Gup;
-    gemm_to<MIXED, T, NW>(acc, Pb(Gp), P(Ui), -1.0);
+    gemm_to<MIXED, T, NW>(acc, Pn(Gp), P(Ui), -1.0);
     store<T, NW>(acc, Gup_i, b, b, b);
     if (ch.Gl) {
-      gemm_to<MIXED, T, NW>(acc, P(Li), Pb(Gp), -1.0);
+      gemm_to<MIXED, T, NW>(acc, P(Li), Pn(Gp), -1.0);
       store<T, NW>(acc, ch.Gl + (size_t)i * bb, b, b, b);
     }
-    if (ch.T || ch.first_row) {
+    if (ch.T || ch.first_row || ch.ckR) {
       gemm_to<MIXED, T, NW>(acc, P(Rb + (size_t)((i - 1) & 1) * bpbp), P(Ui), -1.0);
       store<T, NW>(acc, Rb + (size_t)(i & 1) * bpbp, BP, BP, BP);
       if (ch.first_row) store<T, NW>(acc, ch.first_row + (size_t)i * bb, b, b, b);
+      if (ch.ckR && i % ch.dlen == 0) store<T, NW>(acc, ch.ckR + (size_t)(i / ch.dlen) * bpbp, BP, BP, BP);
+      if (ch.Rlast && i == l - 1) store<T, NW>(acc, ch.Rlast, BP, BP, BP);
     }
     __syncthreads();
-    gemm_to<MIXED, T, NW>(acc, P(Li), Pb(Gup_i), -1.0);
+    gemm_to<MIXED, T, NW>(acc, P(Li), Pn(Gup_i), -1.0);
     add_from<T, NW>(acc, P(g + (size_t)i * bpbp));
     store<T, NW>(acc, ch.Gd + (size_t)i * bb, b, b, b);
     __syncthreads();
@@ -210,6 +232,15 @@ __global__ __launch_bounds__(64 * NW, 1) void rgf_sweep_kernel(SweepArgs a) {
   ch.ws = a.ws + (size_t)e * a.ws_chain;
   ch.l = l;
   ch.b = b;
+  ch.ckP = ch.ckR = ch.Rlast = nullptr;
+  ch.nd = a.nd;
+  ch.dlen = a.dlen > 0 ? a.dlen : 1;
+  if (a.nd > 0) {
+    const size_t bpbp = (size_t)16 * T * 16 * T;
+    ch.ckP = ch.ws + sweep_ws_chain_elems(l, 16 * T);
+    ch.ckR = ch.ckP + (size_t)a.nd * bpbp;
+    ch.Rlast = ch.ckR + (size_t)a.nd * bpbp;
+  }
   rgf_chain<T, NW, MIXED>(ch, sh, red);
 }
 
@@ -284,6 +315,9 @@ __global__ __launch_bounds__(512, 1) void rgf_batched_kernel(BatchArgs a) {
     ch.ws = ws;
     ch.l = l;
     ch.b = b;
+    ch.ckP = ch.ckR = ch.Rlast = nullptr;
+    ch.nd = 0;
+    ch.dlen = 1;
     switch (b >> 4) {
       case 2: rgf_chain<2, 8, MIXED>(ch, sh, red); break;
       case 4: rgf_chain<4, 8, MIXED>(ch, sh, red); break;

@@ -32,7 +32,7 @@ def declared_symbols():
 def test_header_declares_entry_points():
     syms = declared_symbols()
     for s in ("rgf_plan_create", "rgf_plan_destroy", "rgf_solve", "ddrgf_solve", "rgf_batched_plan_create",
-              "rgf_batched_solve"):
+              "rgf_batched_solve", "rgf_backward"):
         assert s in syms
 
 
@@ -55,7 +55,7 @@ def test_plan_workspace_size(l, b, w, ne):
     binding = _lib()
     p = binding.Plan(l, b, w, ne)
     bp = ((b + 15) // 16) * 16
-    assert p.workspace_bytes == (3 * l + 8) * bp * bp * 16 * ne
+    assert p.workspace_bytes == (3 * l + 10) * bp * bp * 16 * ne
     p.close()
 
 
@@ -71,6 +71,8 @@ def test_plan_workspace_size(l, b, w, ne):
     (dict(l=9, b=4, w=2, ne=1, method="ddrgf", domains=2), 2),
     (dict(l=8, b=80, w=2, ne=1, method="ddrgf", domains=2), 2),
     (dict(l=8, b=4, w=1, ne=1, method="ddrgf", domains=5), 1),
+    (dict(l=8, b=4, w=1, ne=1, method="ddrgf", domains=2, want_backward=True), 2),
+    (dict(l=8, b=4, w=1, ne=1, precision="fp32", want_backward=True), 2),
 ])
 def test_plan_validation_errors(args, code):
     binding = _lib()
@@ -91,3 +93,19 @@ def test_solve_rejects_null_and_small_workspace():
     # a sequential plan used with the DDRGF entry point
     assert lib.ddrgf_solve(p.handle, fake, fake, fake, fake, 0.0, fake, None, fake, fake, 1 << 40, None) == 6
     p.close()
+
+
+def test_backward_plan_workspace_and_mismatch():
+    binding = _lib()
+    lib = binding.load()
+    l, b, ne, nd = 256, 64, 4, 8
+    p = binding.Plan(l, b, 1, ne, want_backward=True, checkpoint_domains=nd)
+    plain = binding.Plan(l, b, 1, ne)
+    bpbp = b * b
+    chain = (3 * l + 10 + 2 * nd + 1) * bpbp * 16
+    assert p.workspace_bytes >= chain * ne + ne * nd * (32 + 7) * bpbp * 16 + ne * l * b * 8
+    fake = ctypes.c_void_p(16)
+    # a plan without want_backward cannot run the adjoint
+    assert lib.rgf_backward(plain.handle, fake, fake, fake, fake, fake, fake, 1 << 40, None) == 6
+    assert lib.rgf_backward(p.handle, None, fake, fake, fake, fake, fake, 1 << 40, None) == 1
+    assert lib.rgf_backward(p.handle, fake, fake, fake, fake, fake, fake, 16, None) == 4
