@@ -52,6 +52,50 @@ def ddrgf_interior_flops(l: int, b: int, m: int, ne: int) -> float:
     return tot * 8.0 * float(b) ** 3 * ne
 
 
+def ddrgf_recover_flops(l: int, b: int, m: int, ne: int) -> float:
+    """Flops executed by the DDRGF recovery kernel, 8 b^3 per complex product: per
+    interior of n layers with a left separator, 4 products per layer for
+    V^L_i, V^R_i, 2 per recovered band block (3n - 2 of them) and 4 for the
+    separator couplings; the first interior (no left separator) needs 1, 1 and 1."""
+    base, rem = divmod(l - m, m)
+    tot = 0
+    for k in range(m):
+        n = base + (1 if k < rem else 0)
+        left = k > 0
+        tot += n * (4 if left else 1) + (3 * n - 2) * (2 if left else 1) + (4 if left else 1)
+    return tot * 8.0 * float(b) ** 3 * ne
+
+
+def nrgf_flops_per_energy(l: int, b: int, w: int) -> float:
+    """The paper's op counts for the block n-diagonal sweep (eq. cost_model_general_RGF):
+    with c_i = min(w, i) coupled layers above layer i, the upward pass costs l LU,
+    2 c_i GETRS and c_i^2 GEMM per layer, the downward pass 1 GETRS and 2 c_i^2 + c_i
+    GEMM per layer; the first-row propagation behind T adds c_i GEMM per layer.
+    8/3 b^3 per LU, 8 b^3 per GETRS or GEMM."""
+    b3 = float(b) ** 3
+    tot = 0.0
+    for i in range(l):
+        c = min(w, i)
+        tot += 8.0 / 3.0 + 8.0 * (2 * c + c * c) + 8.0 * (1 + 2 * c * c + c) + 8.0 * c
+    return tot * b3
+
+
+def adjoint_flops(l: int, b: int, ne: int, nd: int) -> float:
+    """Flops of the adjoint kernel, 8 b^3 per complex product: X = Gamma_R R^H Gamma_L
+    (2 per (energy, domain)), P recomputed inside each domain (one product per layer
+    but the domain's last), and per layer R_i (all but the domain's first), X R_i and
+    G_ii P_i."""
+    dlen = -(-l // nd)
+    per = 0
+    for k in range(nd):
+        i0 = k * dlen
+        if i0 >= l:
+            continue
+        n = min(dlen, l - i0)
+        per += 2 + (n - 1) + (n - 1) + 2 * n
+    return per * 8.0 * float(b) ** 3 * ne
+
+
 def algorithmic_bytes(l: int, b: int, ne: int, w: int = 1) -> float:
     """H read once, Sigma_L/R and E read once, G band written once, T written once."""
     blk = 16.0 * b * b
@@ -115,8 +159,9 @@ def main():
     ap.add_argument("--domains", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-workers", type=int, default=0)
-    ap.add_argument("--config", type=int, default=2, choices=[2, 4],
-                    help="2: the 256 x 128 system (default); 4: the batched 64-device workload")
+    ap.add_argument("--config", type=int, default=2, choices=[2, 3, 4, 5],
+                    help="2: the 256 x 128 system (default); 3: the pentadiagonal 512 x 64 system; "
+                         "4: the batched 64-device workload; 5: transmission + adjoint gradient, 256 x 64")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (to scale HBM byte counters)")
     args = ap.parse_args()
@@ -149,13 +194,17 @@ def main():
 
     if args.config == 4:
         return bench_batched(args)
+    if args.config == 3:
+        return bench_ndiag(args)
+    if args.config == 5:
+        return bench_adjoint(args)
     wl = make_config(2)
     l, b, w, ne = wl.l, wl.b, wl.w, wl.ne
     # the CPU leg runs first, in forked workers, before this process touches the GPU
     cpu = None
     if not args.no_cpu_baseline:
         workers = args.cpu_workers or min(16, len(os.sched_getaffinity(0)))
-        cpu = cpu_baseline(wl, max(workers, 8), workers)
+        cpu = cpu_baseline(wl, 2 * workers, workers)
     dev = torch.device("cuda:0")
     H = torch.from_numpy(wl.H).to(dev)
     sL = torch.from_numpy(wl.sigma_L).to(dev)
@@ -188,6 +237,7 @@ def main():
                               "info": info.cpu().tolist()}), flush=True)
             sys.exit(1)
         log(f"{leg}: warmup done; timing")
+        plan.set_timing(True, 16 * args.steps + 16)
         events = []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -203,15 +253,17 @@ def main():
         step_ms = float(np.mean([a.elapsed_time(c) for a, c in events]))
         res = {"value": ne * args.steps / wall, "ms_per_step": 1000.0 * wall / args.steps,
                "gpu_ms_per_step": step_ms}
-        # dominant kernel, timed alone with HIP events on the same stream
-        if leg == "rgf_fp64":
-            res["kernel"] = f"rgf_sweep_kernel (b={b}, l={l}, {ne} chains)"
-            res["kernel_ms"] = step_ms
-            res["flops_per_launch"] = rgf_flops_per_energy(l, b) * ne
-        else:
-            res["kernel"] = f"ddrgf_interior_kernel (b={b}, {args.domains} interiors x {ne} energies)"
-            res["flops_per_launch"] = ddrgf_interior_flops(l, b, args.domains, ne)
-            res["kernel_ms"] = None   # filled from the per-kernel profile when available
+        # per-kernel durations from the library's HIP events on the launch stream
+        times = plan.kernel_times()
+        plan.set_timing(False)
+        res["kernel_ms_avg"] = {k: v[0] / v[1] for k, v in times.items()}
+        flops_of = {"rgf_sweep_kernel": rgf_flops_per_energy(l, b) * ne if method == "rgf" else None,
+                    "ddrgf_interior_kernel": ddrgf_interior_flops(l, b, args.domains, ne),
+                    "ddrgf_recover_kernel": ddrgf_recover_flops(l, b, args.domains, ne)}
+        dom = max(times, key=lambda k: times[k][0])
+        res["kernel"] = dom
+        res["kernel_ms"] = times[dom][0] / times[dom][1]
+        res["flops_per_launch"] = flops_of.get(dom)
         del ws, plan
         torch.cuda.empty_cache()
         if prec != "fp64" and ref_G is not None:
@@ -242,7 +294,7 @@ def main():
         if leg == "rgf_fp64":
             ref_G, ref_T = G.clone(), T.clone()
     best = max(legs, key=lambda k: legs[k]["value"])
-    lead = legs["rgf_fp64"] if "rgf_fp64" in legs else legs[best]
+    lead = legs[best]
     value = legs[best]["value"]
     ms_per_step = legs[best]["ms_per_step"]
     kern_ms = lead["kernel_ms"]
@@ -250,8 +302,8 @@ def main():
     achieved = flops / (kern_ms * 1e-3) / 1e12
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None,
-                "kernel": lead["kernel"], "kernel_ms": round(kern_ms, 3), "flops_per_launch": flops,
-                "algorithmic_bytes_per_launch": algorithmic_bytes(l, b, ne, w)}
+                "kernel": f"{lead['kernel']} ({best})", "kernel_ms": round(kern_ms, 3),
+                "flops_per_launch": flops}
 
     out = {
         "metric": "energy points/sec (selected G^R + T(E))",
@@ -361,6 +413,156 @@ def bench_batched(args):
                      "traffic": None, "kernel": "rgf_batched_kernel<0>", "kernel_ms": round(lead["kernel_ms"], 3),
                      "flops_per_launch": flops},
         "legs": legs,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def _timed_steps(args, step, plan, stream, n_points, label):
+    """Warm up, then time args.steps steps between synchronisations; per-kernel
+    durations come from the library's HIP events on the launch stream."""
+    import numpy as np
+    import torch
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    plan.set_timing(True, 16 * args.steps + 16)
+    evs = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        step()
+        e1.record(stream)
+        evs.append((e0, e1))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    times = plan.kernel_times()
+    plan.set_timing(False)
+    res = {"value": n_points * args.steps / wall, "ms_per_step": 1000.0 * wall / args.steps,
+           "gpu_ms_per_step": float(np.mean([a.elapsed_time(c) for a, c in evs])),
+           "kernel_ms_avg": {k: v[0] / v[1] for k, v in times.items()}}
+    log(f"{label}: {res['value']:.2f} energy points/s, {res['ms_per_step']:.1f} ms per step")
+    return res, times
+
+
+def _roofline(times, flops_of, label):
+    dom = max(times, key=lambda k: times[k][0])
+    kms = times[dom][0] / times[dom][1]
+    fl = flops_of.get(dom)
+    ach = fl / (kms * 1e-3) / 1e12 if fl else None
+    return {"bound": "mfma", "achieved": round(ach, 3) if ach else None, "peak": FP64_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(ach / FP64_PEAK_TFLOPS, 4) if ach else None, "traffic": None,
+            "kernel": f"{dom} ({label})", "kernel_ms": round(kms, 3), "flops_per_launch": fl}
+
+
+def bench_ndiag(args):
+    """The pentadiagonal system (w = 2, 512 layers of 64, 128 energies): native
+    n-diagonal sequential sweep and DDRGF with 16 domains."""
+    import torch
+
+    from paper_2605_19910_amd import binding
+    from workloads import make_config
+
+    wl = make_config(3)
+    l, b, w, ne, m = wl.l, wl.b, wl.w, wl.ne, wl.domains
+    dev = torch.device("cuda:0")
+    H, sL, sR, E = (torch.from_numpy(x).to(dev) for x in (wl.H, wl.sigma_L, wl.sigma_R, wl.energies))
+    G = torch.empty((ne, 2 * w + 1, l, b, b), dtype=torch.complex128, device=dev)
+    T = torch.empty((ne,), dtype=torch.float64, device=dev)
+    info = torch.empty((ne,), dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    legs, rooflines, Ts = {}, {}, {}
+    for leg in ("nrgf_fp64", "ddrgf_fp64"):
+        if leg.startswith("nrgf"):
+            plan = binding.Plan(l, b, w, ne, method="rgf")
+            fn = binding.rgf_solve
+        else:
+            plan = binding.Plan(l, b, w, ne, method="ddrgf", domains=m)
+            fn = binding.ddrgf_solve
+        ws = torch.empty((plan.workspace_bytes,), dtype=torch.uint8, device=dev)
+        log(f"{leg}: workspace {plan.workspace_bytes / 2**30:.1f} GiB")
+
+        def step():
+            fn(plan, H, sL, sR, E, wl.eta_d, G, T, info, ws, stream.cuda_stream)
+
+        res, times = _timed_steps(args, step, plan, stream, ne, leg)
+        res["all_info_zero"] = bool((info == 0).all())
+        Ts[leg] = T.clone()
+        flops_of = {"nrgf_sweep_kernel": nrgf_flops_per_energy(l, b, w) * ne,
+                    # DDRGF runs on the w-layer super-block form (l/w layers of w b)
+                    "ddrgf_interior_kernel": ddrgf_interior_flops(l // w, w * b, m, ne),
+                    "ddrgf_recover_kernel": ddrgf_recover_flops(l // w, w * b, m, ne)}
+        rooflines[leg] = _roofline(times, flops_of, leg)
+        legs[leg] = res
+        del ws, plan
+        torch.cuda.empty_cache()
+    dT = ((Ts["ddrgf_fp64"] - Ts["nrgf_fp64"]).abs() / torch.clamp(Ts["nrgf_fp64"].abs(), min=1.0)).max().item()
+    best = max(legs, key=lambda k: legs[k]["value"])
+    out = {
+        "metric": "energy points/sec (selected G^R + T(E))", "value": round(legs[best]["value"], 3),
+        "unit": "energy points/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(legs[best]["ms_per_step"], 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "c128 (f64)",
+        "data": "synthetic: seeded random Hermitian block pentadiagonal band, closed-form lead self-energies",
+        "config": {"workload": f"block pentadiagonal (w=2, next-nearest blocks x0.3), l={l}, b={b}, "
+                               f"{ne} energies in [-2,2], eta=1e-4, seed 103",
+                   "method": {"nrgf_fp64": "native block n-diagonal sweep",
+                              "ddrgf_fp64": f"DDRGF, {m} domains, separators of w layers"}[best]},
+        "roofline": rooflines[best],
+        "legs": legs, "rooflines": rooflines, "T_rel_diff_ddrgf_vs_sequential": dT,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_adjoint(args):
+    """Transmission and its gradient with respect to every on-site energy: the
+    256 x 64 system over 256 energies, forward sweep with 8 checkpoint domains,
+    then the adjoint kernel (L = sum_E T(E))."""
+    import torch
+
+    from paper_2605_19910_amd import binding
+    from workloads import make_config
+
+    wl = make_config(5)
+    l, b, ne = wl.l, wl.b, wl.ne
+    nd = wl.domains or 8
+    dev = torch.device("cuda:0")
+    H, sL, sR, E = (torch.from_numpy(x).to(dev) for x in (wl.H, wl.sigma_L, wl.sigma_R, wl.energies))
+    G = torch.empty((ne, 3, l, b, b), dtype=torch.complex128, device=dev)
+    T = torch.empty((ne,), dtype=torch.float64, device=dev)
+    info = torch.empty((ne,), dtype=torch.int32, device=dev)
+    dLdT = torch.ones((ne,), dtype=torch.float64, device=dev)
+    grad = torch.empty((l * b,), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    plan = binding.Plan(l, b, 1, ne, method="rgf", want_backward=True, checkpoint_domains=nd)
+    ws = torch.empty((plan.workspace_bytes,), dtype=torch.uint8, device=dev)
+    log(f"adjoint: workspace {plan.workspace_bytes / 2**30:.1f} GiB")
+
+    def step():
+        binding.rgf_solve(plan, H, sL, sR, E, wl.eta_d, G, T, info, ws, stream.cuda_stream)
+        binding.rgf_backward(plan, sL, sR, G, dLdT, grad, ws, stream.cuda_stream)
+
+    res, times = _timed_steps(args, step, plan, stream, ne, "forward+adjoint")
+    res["all_info_zero"] = bool((info == 0).all())
+    res["grad_finite"] = bool(torch.isfinite(grad).all())
+    flops_of = {"rgf_sweep_kernel": rgf_flops_per_energy(l, b) * ne,
+                "rgf_adjoint_kernel": adjoint_flops(l, b, ne, nd)}
+    roof = _roofline(times, flops_of, "forward+adjoint")
+    adj = {k: v for k, v in times.items() if k == "rgf_adjoint_kernel"}
+    out = {
+        "metric": "energy points/sec (T(E) + dT/d(on-site energies) via the adjoint)",
+        "value": round(res["value"], 3), "unit": "energy points/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(res["ms_per_step"], 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "c128 (f64)",
+        "data": "synthetic: seeded random Hermitian block-tridiagonal band, closed-form lead self-energies",
+        "config": {"workload": f"block-tridiagonal, l={l}, b={b}, {ne} energies in [-2,2], eta=1e-6, "
+                               f"seed 105; gradient w.r.t. {l * b} on-site energies, {nd} checkpoint domains",
+                   "method": "sequential RGF forward + adjoint kernel"},
+        "roofline": roof,
+        "adjoint_roofline": _roofline(adj, flops_of, "adjoint only") if adj else None,
+        "legs": {"forward_adjoint_fp64": res},
     }
     print(json.dumps(out), flush=True)
 

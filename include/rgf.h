@@ -183,6 +183,39 @@ rgf_status_t rgf_backward(rgf_plan_t plan, const void* sigma_L, const void* sigm
                           const double* dL_dT, double* d_onsite, void* workspace, size_t workspace_bytes,
                           void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Per-kernel timing (measurement aid; not part of the method).
+ *
+ * rgf_plan_set_timing(plan, 1, max_marks) creates a pool of max_marks HIP events
+ * owned by the plan (host-side creation; call it outside graph capture).  While
+ * timing is enabled, rgf_solve, ddrgf_solve and rgf_backward record one event on
+ * their stream before their first kernel and one after every kernel they launch,
+ * so a kernel's duration is the time between the event before it and the event
+ * after it on that stream.  Events beyond the pool are not recorded (the next
+ * query reports how many were dropped).  Batched solves are not timed.
+ * rgf_plan_set_timing(plan, 0, 0) destroys the pool.  Returns RGF_ERR_INVALID_ARG
+ * for a NULL plan or max_marks < 2 when enabling, RGF_ERR_HIP if event creation
+ * fails.
+ *
+ * rgf_plan_kernel_times waits for the last recorded event (the host blocks), sums
+ * the durations per kernel name over every solve since the previous query, writes
+ * up to max_entries entries in order of first appearance, sets *n_entries to the
+ * number of distinct kernels (which may exceed max_entries) and *dropped (may be
+ * NULL) to the number of marks lost to a full pool, and empties the pool.
+ * Returns RGF_ERR_INVALID_ARG when timing is not enabled or out / n_entries is
+ * NULL, RGF_ERR_HIP if an event query fails.  Must not run concurrently with a
+ * solve on the same plan.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  char name[48];       /* kernel name, NUL-terminated */
+  double total_ms;     /* summed duration of its launches */
+  int64_t launches;    /* number of launches timed */
+} rgf_kernel_time_t;
+
+rgf_status_t rgf_plan_set_timing(rgf_plan_t plan, int32_t enable, int32_t max_marks);
+rgf_status_t rgf_plan_kernel_times(rgf_plan_t plan, rgf_kernel_time_t* out, int32_t max_entries,
+                                   int32_t* n_entries, int32_t* dropped);
+
 /* Static text of a status code. */
 const char* rgf_status_string(rgf_status_t status);
 

@@ -49,6 +49,10 @@ BATCH_DEVICE_DTYPE = [("H", "<u8"), ("sigma_L", "<u8"), ("sigma_R", "<u8"), ("en
 SCHEDULE = {"longest_first": 0, "input_order": 1, "interleaved": 2}
 
 
+class KernelTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 48), ("total_ms", ctypes.c_double), ("launches", ctypes.c_int64)]
+
+
 class RgfError(RuntimeError):
     def __init__(self, fn: str, code: int):
         super().__init__(f"{fn}: {STATUS.get(code, 'unknown status')} (code {code})")
@@ -86,6 +90,11 @@ def load() -> ctypes.CDLL:
     lib.rgf_batched_solve.restype = ctypes.c_int
     lib.rgf_backward.argtypes = [_VP, _VP, _VP, _VP, _VP, _VP, _VP, ctypes.c_size_t, _VP]
     lib.rgf_backward.restype = ctypes.c_int
+    lib.rgf_plan_set_timing.argtypes = [_VP, ctypes.c_int32, ctypes.c_int32]
+    lib.rgf_plan_set_timing.restype = ctypes.c_int
+    lib.rgf_plan_kernel_times.argtypes = [_VP, ctypes.POINTER(KernelTime), ctypes.c_int32,
+                                          ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+    lib.rgf_plan_kernel_times.restype = ctypes.c_int
     lib.rgf_status_string.argtypes = [ctypes.c_int]
     lib.rgf_status_string.restype = ctypes.c_char_p
     lib.rgf_version.argtypes = []
@@ -112,6 +121,24 @@ class Plan:
         self.workspace_bytes = int(ws.value)
         self.method = method
         self.l, self.b, self.w, self.ne = l, b, w, ne
+
+    def set_timing(self, enable: bool = True, max_marks: int = 256) -> None:
+        """Record a HIP event after every kernel this plan's solves launch."""
+        st = self.lib.rgf_plan_set_timing(self.handle, 1 if enable else 0, int(max_marks) if enable else 0)
+        if st != RGF_OK:
+            raise RgfError("rgf_plan_set_timing", st)
+
+    def kernel_times(self, max_entries: int = 32) -> dict:
+        """{kernel name: (total ms, launches)} since the previous call (blocks the host)."""
+        out = (KernelTime * max_entries)()
+        n = ctypes.c_int32(0)
+        dropped = ctypes.c_int32(0)
+        st = self.lib.rgf_plan_kernel_times(self.handle, out, max_entries, ctypes.byref(n), ctypes.byref(dropped))
+        if st != RGF_OK:
+            raise RgfError("rgf_plan_kernel_times", st)
+        if dropped.value:
+            raise RuntimeError(f"{dropped.value} timing marks dropped: enlarge max_marks")
+        return {out[i].name.decode(): (out[i].total_ms, int(out[i].launches)) for i in range(min(n.value, max_entries))}
 
     def close(self):
         if self.handle:

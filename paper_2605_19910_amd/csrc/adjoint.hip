@@ -148,8 +148,11 @@ static hipError_t launch_adj_T(const AdjArgs& a, hipStream_t s) {
   hipLaunchKernelGGL((rgf_adjoint_kernel<T, NW>), dim3(a.ne * a.nd), dim3(64 * NW), 0, s, a);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
+  ktime_mark("rgf_adjoint_kernel", s);
   hipLaunchKernelGGL(adjoint_sum_kernel, dim3(256), dim3(256), 0, s, a);
-  return hipGetLastError();
+  if ((err = hipGetLastError()) != hipSuccess) return err;
+  ktime_mark("adjoint_sum_kernel", s);
+  return hipSuccess;
 }
 
 hipError_t launch_rgf_adjoint(const AdjArgs& a, hipStream_t s) {

@@ -1,5 +1,6 @@
 // C ABI: plan validation, workspace layout and dispatch to the HIP kernels.
 #include <algorithm>
+#include <cstring>
 #include <mutex>
 #include <new>
 #include <vector>
@@ -37,7 +38,47 @@ struct rgf_plan_s {
   void* g_ws = nullptr;
   double g_eta = 0.0;
   hipStream_t g_stream = nullptr;
+  // per-kernel timing: event pool, the kernel each event closes (nullptr = the
+  // solve's start mark), marks used and dropped since the last query
+  bool timing = false;
+  std::vector<hipEvent_t> tev;
+  std::vector<const char*> tname;
+  int tused = 0, tdropped = 0;
 };
+
+namespace {
+// plan whose solve is being queued on this host thread, when it is timed
+thread_local rgf_plan_s* t_timed = nullptr;
+
+void record_mark(rgf_plan_s* p, const char* name, hipStream_t s) {
+  if (p->tused >= (int)p->tev.size()) {
+    ++p->tdropped;
+    return;
+  }
+  if (hipEventRecord(p->tev[p->tused], s) != hipSuccess) {
+    ++p->tdropped;
+    return;
+  }
+  p->tname[p->tused++] = name;
+}
+
+// Marks the start of a solve and routes the launchers' marks to the plan.
+struct TimedScope {
+  explicit TimedScope(rgf_plan_s* p, hipStream_t s) {
+    if (p->timing) {
+      t_timed = p;
+      record_mark(p, nullptr, s);
+    }
+  }
+  ~TimedScope() { t_timed = nullptr; }
+};
+}  // namespace
+
+namespace rgfk {
+void ktime_mark(const char* kernel, hipStream_t s) {
+  if (t_timed) record_mark(t_timed, kernel, s);
+}
+}  // namespace rgfk
 
 namespace {
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -151,6 +192,7 @@ rgf_status_t rgf_plan_destroy(rgf_plan_t plan) {
     hipGraphDestroy(plan->graph);
   }
   if (plan->d_index) hipFree(plan->d_index);
+  for (hipEvent_t ev : plan->tev) hipEventDestroy(ev);
   delete plan;
   return RGF_OK;
 }
@@ -296,6 +338,7 @@ rgf_status_t rgf_solve(rgf_plan_t plan, const void* H, const void* sigma_L, cons
   if (!H || !sigma_L || !sigma_R || !energies || !G || !info) return RGF_ERR_INVALID_ARG;
   if (!workspace || workspace_bytes < plan->ws_bytes) return RGF_ERR_WORKSPACE_TOO_SMALL;
   const rgf_desc_t& d = plan->d;
+  TimedScope timed(plan, static_cast<hipStream_t>(stream));
   if (d.half_bandwidth > 1) {
     rgfk::NSweepArgs n{};
     n.H = static_cast<const double2*>(H);
@@ -352,6 +395,7 @@ rgf_status_t ddrgf_solve(rgf_plan_t plan, const void* H, const void* sigma_L, co
   const rgf_desc_t& d = plan->d;
   char* ws = static_cast<char*>(workspace);
   hipStream_t st = static_cast<hipStream_t>(stream);
+  TimedScope timed(plan, st);
   const int w = (int)d.half_bandwidth;
   rgfk::FuseArgs f{};
   if (w > 1) {
@@ -406,6 +450,7 @@ rgf_status_t rgf_backward(rgf_plan_t plan, const void* sigma_L, const void* sigm
   if (plan->batched || !plan->d.want_backward) return RGF_ERR_PLAN_MISMATCH;
   if (!sigma_L || !sigma_R || !G || !dL_dT || !d_onsite) return RGF_ERR_INVALID_ARG;
   if (!workspace || workspace_bytes < plan->ws_bytes) return RGF_ERR_WORKSPACE_TOO_SMALL;
+  TimedScope timed(plan, static_cast<hipStream_t>(stream));
   char* ws = static_cast<char*>(workspace);
   rgfk::AdjArgs a{};
   a.sigL = static_cast<const double2*>(sigma_L);
@@ -425,6 +470,73 @@ rgf_status_t rgf_backward(rgf_plan_t plan, const void* sigma_L, const void* sigm
   a.dlen = plan->dlen;
   hipError_t e = rgfk::launch_rgf_adjoint(a, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? RGF_OK : RGF_ERR_HIP;
+}
+
+rgf_status_t rgf_plan_set_timing(rgf_plan_t plan, int32_t enable, int32_t max_marks) {
+  if (!plan) return RGF_ERR_INVALID_ARG;
+  for (hipEvent_t ev : plan->tev) hipEventDestroy(ev);
+  plan->tev.clear();
+  plan->tname.clear();
+  plan->tused = plan->tdropped = 0;
+  plan->timing = false;
+  if (!enable) return RGF_OK;
+  if (max_marks < 2) return RGF_ERR_INVALID_ARG;
+  try {
+    plan->tev.reserve(max_marks);
+    plan->tname.assign(max_marks, nullptr);
+  } catch (const std::bad_alloc&) {
+    return RGF_ERR_OUT_OF_MEMORY;
+  }
+  for (int i = 0; i < max_marks; ++i) {
+    hipEvent_t ev;
+    if (hipEventCreate(&ev) != hipSuccess) {
+      for (hipEvent_t x : plan->tev) hipEventDestroy(x);
+      plan->tev.clear();
+      return RGF_ERR_HIP;
+    }
+    plan->tev.push_back(ev);
+  }
+  plan->timing = true;
+  return RGF_OK;
+}
+
+rgf_status_t rgf_plan_kernel_times(rgf_plan_t plan, rgf_kernel_time_t* out, int32_t max_entries,
+                                   int32_t* n_entries, int32_t* dropped) {
+  if (!plan || !plan->timing || !out || !n_entries) return RGF_ERR_INVALID_ARG;
+  const int used = plan->tused;
+  rgf_status_t st = RGF_OK;
+  std::vector<const char*> names;
+  std::vector<double> ms;
+  std::vector<int64_t> cnt;
+  if (used > 0 && hipEventSynchronize(plan->tev[used - 1]) != hipSuccess) st = RGF_ERR_HIP;
+  for (int i = 1; i < used && st == RGF_OK; ++i) {
+    const char* k = plan->tname[i];
+    if (!k) continue;   // start mark of the next solve
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, plan->tev[i - 1], plan->tev[i]) != hipSuccess) {
+      st = RGF_ERR_HIP;
+      break;
+    }
+    size_t j = 0;
+    while (j < names.size() && std::strcmp(names[j], k) != 0) ++j;
+    if (j == names.size()) {
+      names.push_back(k);
+      ms.push_back(0.0);
+      cnt.push_back(0);
+    }
+    ms[j] += t;
+    cnt[j] += 1;
+  }
+  *n_entries = (int32_t)names.size();
+  if (dropped) *dropped = plan->tdropped;
+  for (size_t j = 0; j < names.size() && (int)j < max_entries; ++j) {
+    std::memset(out[j].name, 0, sizeof out[j].name);
+    std::strncpy(out[j].name, names[j], sizeof out[j].name - 1);
+    out[j].total_ms = ms[j];
+    out[j].launches = cnt[j];
+  }
+  plan->tused = plan->tdropped = 0;
+  return st;
 }
 
 const char* rgf_status_string(rgf_status_t s) {

@@ -396,8 +396,10 @@ static hipError_t launch_dd_T(const DDArgs& a, hipStream_t s) {
     hipLaunchKernelGGL((ddrgf_interior_kernel<T, NW, 0>), dim3(chains), dim3(64 * NW), 0, s, a);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
+  ktime_mark("ddrgf_interior_kernel", s);
   hipLaunchKernelGGL((ddrgf_schur_kernel<T, NW>), dim3(chains), dim3(64 * NW), 0, s, a);
   if ((err = hipGetLastError()) != hipSuccess) return err;
+  ktime_mark("ddrgf_schur_kernel", s);
   SweepArgs r{};
   r.H = a.MS;
   r.h_stride = (size_t)3 * a.m * a.b * a.b;
@@ -421,8 +423,11 @@ static hipError_t launch_dd_T(const DDArgs& a, hipStream_t s) {
   else
     hipLaunchKernelGGL((ddrgf_recover_kernel<T, NW, 0>), dim3(chains), dim3(64 * NW), 0, s, a);
   if ((err = hipGetLastError()) != hipSuccess) return err;
+  ktime_mark("ddrgf_recover_kernel", s);
   hipLaunchKernelGGL((ddrgf_finalize_kernel<T, NW>), dim3(a.ne), dim3(64 * NW), 0, s, a);
-  return hipGetLastError();
+  if ((err = hipGetLastError()) != hipSuccess) return err;
+  ktime_mark("ddrgf_finalize_kernel", s);
+  return hipSuccess;
 }
 
 hipError_t launch_ddrgf(const DDArgs& a, hipStream_t s) {

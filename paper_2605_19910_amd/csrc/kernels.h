@@ -53,6 +53,10 @@ struct AdjArgs {
 };
 
 hipError_t launch_rgf_adjoint(const AdjArgs& a, hipStream_t s);
+
+// Per-kernel timing: when the solve running on this host thread belongs to a plan
+// with timing enabled, records an event on s after the named kernel's launch.
+void ktime_mark(const char* kernel, hipStream_t s);
 // g[l], U[l], L[l], R[2], Gamma_L, Gamma_R, X1, two blocks for the pivot refinement,
 // one for G_{i-1,i} when the off-diagonal output is not wanted, two for P
 __host__ __device__ inline size_t sweep_ws_chain_elems(int l, int bp) {

@@ -135,7 +135,9 @@ template <int T>
 static hipError_t launch_n_T(const NSweepArgs& a, hipStream_t s) {
   constexpr int NW = T >= 7 ? 8 : 4;
   hipLaunchKernelGGL((nrgf_sweep_kernel<T, NW>), dim3(a.ne), dim3(64 * NW), 0, s, a);
-  return hipGetLastError();
+  hipError_t err = hipGetLastError();
+  if (err == hipSuccess) ktime_mark("nrgf_sweep_kernel", s);
+  return err;
 }
 
 hipError_t launch_nrgf_sweep(const NSweepArgs& a, hipStream_t s) {
@@ -219,8 +221,11 @@ hipError_t launch_fuse(const FuseArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(fuse_band_kernel, dim3(2048), dim3(256), 0, s, a);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
+  ktime_mark("fuse_band_kernel", s);
   hipLaunchKernelGGL(fuse_sigma_kernel, dim3(1024), dim3(256), 0, s, a);
-  return hipGetLastError();
+  if ((err = hipGetLastError()) != hipSuccess) return err;
+  ktime_mark("fuse_sigma_kernel", s);
+  return hipSuccess;
 }
 
 __global__ void unfuse_info_kernel(FuseArgs a) {
@@ -236,8 +241,11 @@ hipError_t launch_unfuse(const FuseArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(unfuse_band_kernel, dim3(4096), dim3(256), 0, s, a);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
+  ktime_mark("unfuse_band_kernel", s);
   hipLaunchKernelGGL(unfuse_info_kernel, dim3((a.ne + 255) / 256), dim3(256), 0, s, a);
-  return hipGetLastError();
+  if ((err = hipGetLastError()) != hipSuccess) return err;
+  ktime_mark("unfuse_info_kernel", s);
+  return hipSuccess;
 }
 
 }  // namespace rgfk

@@ -251,7 +251,9 @@ static hipError_t launch_T(const SweepArgs& a, hipStream_t s) {
     hipLaunchKernelGGL((rgf_sweep_kernel<T, NW, 1>), dim3(a.chains), dim3(64 * NW), 0, s, a);
   else
     hipLaunchKernelGGL((rgf_sweep_kernel<T, NW, 0>), dim3(a.chains), dim3(64 * NW), 0, s, a);
-  return hipGetLastError();
+  hipError_t err = hipGetLastError();
+  if (err == hipSuccess) ktime_mark("rgf_sweep_kernel", s);
+  return err;
 }
 
 hipError_t launch_rgf_sweep(const SweepArgs& a, hipStream_t s) {

@@ -32,7 +32,7 @@ def declared_symbols():
 def test_header_declares_entry_points():
     syms = declared_symbols()
     for s in ("rgf_plan_create", "rgf_plan_destroy", "rgf_solve", "ddrgf_solve", "rgf_batched_plan_create",
-              "rgf_batched_solve", "rgf_backward"):
+              "rgf_batched_solve", "rgf_backward", "rgf_plan_set_timing", "rgf_plan_kernel_times"):
         assert s in syms
 
 
@@ -109,3 +109,21 @@ def test_backward_plan_workspace_and_mismatch():
     assert lib.rgf_backward(plain.handle, fake, fake, fake, fake, fake, fake, 1 << 40, None) == 6
     assert lib.rgf_backward(p.handle, None, fake, fake, fake, fake, fake, 1 << 40, None) == 1
     assert lib.rgf_backward(p.handle, fake, fake, fake, fake, fake, fake, 16, None) == 4
+
+
+def test_timing_argument_errors():
+    """Timing queries on a plan without timing, and a pool too small to hold a
+    start and an end mark, are rejected on the host (no HIP call is made)."""
+    binding = _lib()
+    lib = binding.load()
+    p = binding.Plan(4, 4, 1, 1)
+    n = ctypes.c_int32(-1)
+    out = (binding.KernelTime * 4)()
+    assert lib.rgf_plan_kernel_times(p.handle, out, 4, ctypes.byref(n), None) == 1
+    assert lib.rgf_plan_kernel_times(None, out, 4, ctypes.byref(n), None) == 1
+    assert lib.rgf_plan_set_timing(p.handle, 1, 1) == 1
+    assert lib.rgf_plan_set_timing(None, 1, 16) == 1
+    assert lib.rgf_plan_set_timing(p.handle, 0, 0) == 0     # disabling is always fine
+    with pytest.raises(binding.RgfError):
+        p.kernel_times()
+    p.close()
