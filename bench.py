@@ -28,6 +28,30 @@ if ROOT not in sys.path:
 FP64_PEAK_TFLOPS = 78.6      # MI355X dense FP64 MFMA
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per launch of a kernel, from two rocprofv3 --pmc passes (FETCH_SIZE, then
+# WRITE_SIZE, KiB per dispatch) scaled by what the same counters read for a plain copy of
+# known size.  Valid only for the kernel sources the counters were taken on: their sha256
+# is stored with the figure, and a mismatch reports null.
+TRAFFIC_SOURCES = ("paper_2605_19910_amd/csrc/block_engine.h", "paper_2605_19910_amd/csrc/kernels.h",
+                   "paper_2605_19910_amd/csrc/ddrgf.hip", "paper_2605_19910_amd/csrc/rgf_sweep.hip")
+MEASURED_TRAFFIC = {}
+
+
+def sources_digest() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def traffic_for(kernel: str, workload: str):
+    rec = MEASURED_TRAFFIC.get((kernel, workload))
+    if rec is None or rec["sha256"] != sources_digest():
+        return None
+    return rec["bytes"]
+
 
 def rgf_flops_per_energy(l: int, b: int) -> float:
     """Algorithmic flops of one RGF energy point: the paper's op counts (l LU,
@@ -304,6 +328,7 @@ def main():
                 "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None,
                 "kernel": f"{lead['kernel']} ({best})", "kernel_ms": round(kern_ms, 3),
                 "flops_per_launch": flops}
+    roofline["traffic"] = traffic_for(lead["kernel"], f"c2/{best}")
 
     out = {
         "metric": "energy points/sec (selected G^R + T(E))",
