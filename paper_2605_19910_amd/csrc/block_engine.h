@@ -106,9 +106,10 @@ __device__ __forceinline__ void acc_zero(Acc<T, NW>& a) {
     }
 }
 
-// acc += sgn * A * B, A and B logical bp x bp operands.
+// acc += sgn * A * B for operands that may be conjugate-transposed: fragments
+// read straight from global memory one k-step ahead.
 template <int T, int NW>
-__device__ __forceinline__ void mma(Acc<T, NW>& acc, const Opnd& A, const Opnd& B, double sgn) {
+__device__ __forceinline__ void mma_conj(Acc<T, NW>& acc, const Opnd& A, const Opnd& B, double sgn) {
   constexpr int RR = Acc<T, NW>::RR;
   constexpr int RC = Acc<T, NW>::RC;
   constexpr int BP = 16 * T;
@@ -153,6 +154,86 @@ __device__ __forceinline__ void mma(Acc<T, NW>& acc, const Opnd& A, const Opnd& 
     for (int r = 0; r < RR; ++r) a[r] = an[r];
 #pragma unroll
     for (int c = 0; c < RC; ++c) b[c] = bn[c];
+  }
+}
+
+__device__ __forceinline__ double2 opnd_get_n(const Opnd& o, int i, int j) {
+  return (i < o.nr && j < o.nc) ? o.p[(size_t)i * o.ld + j] : make_double2(0.0, 0.0);
+}
+
+// acc += sgn * A * B, A and B logical bp x bp operands.  Non-conjugated operands
+// stream from global memory two k-steps ahead of the MFMAs (the fragments of a
+// k-step are in flight for two k-steps of MFMA work); each accumulator receives
+// its four real products in the same order as in mma_conj, so both give
+// bitwise the same result.
+template <int T, int NW>
+__device__ __forceinline__ void mma(Acc<T, NW>& acc, const Opnd& A, const Opnd& B, double sgn) {
+  if (A.conjT || B.conjT) {
+    mma_conj<T, NW>(acc, A, B, sgn);
+    return;
+  }
+  constexpr int RR = Acc<T, NW>::RR;
+  constexpr int RC = Acc<T, NW>::RC;
+  constexpr int BP = 16 * T;
+  constexpr int NKS = BP / 4;       // k-steps, a multiple of 4
+  const int l = lane_id();
+  int tr0, tc0;
+  tile_origin<T, NW>(tr0, tc0);
+  const int li = l & 15, lk = l >> 4;
+  double2 a[2][RR], b[2][RC];
+#pragma unroll
+  for (int d = 0; d < 2; ++d) {
+#pragma unroll
+    for (int r = 0; r < RR; ++r)
+      a[d][r] = (tr0 + r < T) ? opnd_get_n(A, 16 * (tr0 + r) + li, 4 * d + lk) : make_double2(0.0, 0.0);
+#pragma unroll
+    for (int c = 0; c < RC; ++c)
+      b[d][c] = (tc0 + c < T) ? opnd_get_n(B, 4 * d + lk, 16 * (tc0 + c) + li) : make_double2(0.0, 0.0);
+  }
+  for (int ks0 = 0; ks0 < NKS; ks0 += 2) {
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+      const int ks = ks0 + d;
+      double2 ac[RR], bc[RC];
+#pragma unroll
+      for (int r = 0; r < RR; ++r) ac[r] = a[d][r];
+#pragma unroll
+      for (int c = 0; c < RC; ++c) {
+        bc[c] = b[d][c];
+        bc[c].x *= sgn;
+        bc[c].y *= sgn;
+      }
+      if (ks + 2 < NKS) {
+        const int k = 4 * (ks + 2) + lk;
+#pragma unroll
+        for (int r = 0; r < RR; ++r)
+          a[d][r] = (tr0 + r < T) ? opnd_get_n(A, 16 * (tr0 + r) + li, k) : make_double2(0.0, 0.0);
+#pragma unroll
+        for (int c = 0; c < RC; ++c)
+          b[d][c] = (tc0 + c < T) ? opnd_get_n(B, k, 16 * (tc0 + c) + li) : make_double2(0.0, 0.0);
+      }
+      // first terms of every tile, then the second ones: consecutive MFMAs are independent
+#pragma unroll
+      for (int r = 0; r < RR; ++r) {
+        if (tr0 + r >= T) continue;
+#pragma unroll
+        for (int c = 0; c < RC; ++c) {
+          if (tc0 + c >= T) continue;
+          acc.re[r][c] = mfma(ac[r].x, bc[c].x, acc.re[r][c]);
+          acc.im[r][c] = mfma(ac[r].x, bc[c].y, acc.im[r][c]);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < RR; ++r) {
+        if (tr0 + r >= T) continue;
+#pragma unroll
+        for (int c = 0; c < RC; ++c) {
+          if (tc0 + c >= T) continue;
+          acc.re[r][c] = mfma(-ac[r].y, bc[c].y, acc.re[r][c]);
+          acc.im[r][c] = mfma(ac[r].y, bc[c].x, acc.im[r][c]);
+        }
+      }
+    }
   }
 }
 
@@ -385,13 +466,27 @@ __device__ __forceinline__ void add_identity(Acc<T, NW>& acc) {
     }
 }
 
+// Pivot-search key of a row whose candidate has magnitude k (k < 0: non-finite):
+// unpivoted rows rank above pivoted rows and lanes without a row (key 0),
+// non-finite candidates below finite ones; finite ones by the top 57 bits of k,
+// then by lowest row (the row, < 128, fills the low 7 bits).
+__device__ __forceinline__ uint64_t pivot_key(double k, int row) {
+  const uint64_t hi = k < 0.0 ? 1 : ((uint64_t)__double_as_longlong(k) >> 7) + 2;
+  return (hi << 7) | (uint64_t)(127 - row);
+}
+
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int off) {
+  const int lo = __shfl_xor((int)(uint32_t)v, off, 64);
+  const int hi = __shfl_xor((int)(uint32_t)(v >> 32), off, 64);
+  return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+
 // LDS scratch of the Gauss-Jordan inversion.
 struct GJShared {
   double2 pn[MAXBP][PNLD];     // current 16-column panel (all rows)
   double2 rw[16][MAXBP];       // the panel's pivot rows, as they were before the panel
   int rowsel[MAXBP];           // rowsel[c] = row chosen as pivot for column c
   int slot[MAXBP];             // slot[row] = position of row among the panel pivots, or -1
-  int pivoted[MAXBP];
   int rowdst[MAXBP];
   int bad;                     // nonzero: a pivot was zero or non-finite
 };
@@ -415,7 +510,10 @@ __device__ __forceinline__ void gj_invert(Acc<T, NW>& acc, double2* g, GJShared&
   int tr0, tc0;
   tile_origin<T, NW>(tr0, tc0);
 
-  for (int i = t; i < BP; i += NT) { sh.pivoted[i] = 0; sh.slot[i] = -1; }
+  for (int i = t; i < BP; i += NT) sh.slot[i] = -1;
+  // pivoted flags of this lane's candidate rows l + 64 q (every wave tracks all pivots)
+  constexpr int NQ = (BP + 63) / 64;
+  unsigned pivmask = 0;
   if (t == 0) sh.bad = 0;
   __syncthreads();
 
@@ -439,30 +537,29 @@ __device__ __forceinline__ void gj_invert(Acc<T, NW>& acc, double2* g, GJShared&
 
     // 2. sweep the 16 panel columns (restricted to the panel)
     for (int ci = 0; ci < 16; ++ci) {
-      // pivot search, done redundantly by every wave
-      double best = -2.0;
-      int bidx = BP;
-      int nonfinite = 0;
-      for (int row = l; row < BP; row += 64) {
-        double key;
-        if (sh.pivoted[row]) {
-          key = -2.0;
-        } else {
-          double v = cabs1(sh.pn[row][ci]);
+      // pivot search, done redundantly by every wave: argmax of |re| + |im| over
+      // the unpivoted rows (ties: lowest row) as one 64-bit maximum
+      uint64_t u = 0;
+      int nf = 0;
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const int row = l + 64 * q;
+        if (row < BP && !((pivmask >> q) & 1)) {
+          const double v = cabs1(sh.pn[row][ci]);
           const bool fin = (v == v && v <= 1.0e300);
-          nonfinite |= fin ? 0 : 1;
-          key = fin ? v : -1.0;
+          nf |= fin ? 0 : 1;
+          const uint64_t kq = pivot_key(fin ? v : -1.0, row);
+          u = kq > u ? kq : u;
         }
-        if (key > best || (key == best && row < bidx)) { best = key; bidx = row; }
       }
 #pragma unroll
       for (int off = 32; off >= 1; off >>= 1) {
-        double ob = __shfl_xor(best, off, 64);
-        int oi = __shfl_xor(bidx, off, 64);
-        nonfinite |= __shfl_xor(nonfinite, off, 64);
-        if (ob > best || (ob == best && oi < bidx)) { best = ob; bidx = oi; }
+        const uint64_t o = shfl_xor_u64(u, off);
+        u = o > u ? o : u;
       }
-      const int pr = bidx;
+      const bool col_bad = (u >> 7) <= 2 || __ballot(nf) != 0;   // zero or non-finite candidates
+      const int pr = 127 - (int)(u & 127);
+      if ((pr & 63) == l) pivmask |= 1u << (pr >> 6);
       const double2 p = sh.pn[pr][ci];
       const double2 prj = sh.pn[pr][pj];
       double2 pci[PM];
@@ -495,10 +592,9 @@ __device__ __forceinline__ void gj_invert(Acc<T, NW>& acc, double2* g, GJShared&
         sh.pn[i][pj] = nv;
       }
       if (t == 0) {
-        sh.pivoted[pr] = 1;
         sh.rowsel[16 * kt + ci] = pr;
         sh.slot[pr] = ci;
-        if (!(best > 0.0) || nonfinite) sh.bad = 1;
+        if (col_bad) sh.bad = 1;
       }
       __syncthreads();
     }
