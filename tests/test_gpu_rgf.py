@@ -52,9 +52,11 @@ def rel(a, b):
 
 def check_energies(wl, G, T, info, energies, eta_d=None, conditioned=False):
     """Compare with the oracle.  ``conditioned``: the bound is max(1e-10, 2 e_noise),
-    where e_noise is the distance between the oracle and a second oracle run whose
-    Schur pivots carry independent u-sized perturbations: the rounding spread of
-    the block elimination itself (no pivoting across blocks) at this energy."""
+    where e_noise is the largest distance between the oracle and three further oracle
+    runs whose Schur pivots carry independent u-sized perturbations: the rounding
+    spread of the block elimination itself (no pivoting across blocks) at this
+    energy.  One such sample underestimates the spread's tail (eight samples at one
+    ill-conditioned energy range over a factor 3), hence the maximum of three."""
     eta_d = wl.eta_d if eta_d is None else eta_d
     assert np.all(info == 0), info
     for e in energies:
@@ -63,12 +65,20 @@ def check_energies(wl, G, T, info, energies, eta_d=None, conditioned=False):
         ref = r["G"]
         Tref = oracle.transmission(r["row0"][wl.l - 1], wl.sigma_L[e], wl.sigma_R[e])
         tol = TOL
-        if conditioned:
-            rn = oracle.rgf(*args, extras=True, pivot_noise=1000 + e)
-            Tn = oracle.transmission(rn["row0"][wl.l - 1], wl.sigma_L[e], wl.sigma_R[e])
-            e_noise = max(rel(rn["G"], ref), abs(Tn - Tref) / max(1.0, abs(Tref)))
-            tol = max(TOL, 2.0 * e_noise)
         err = rel(mask_band(G[e], wl.w), ref)
+        terr = abs(T[e] - Tref) / max(1.0, abs(Tref))
+        if conditioned:
+            # samples are drawn until the bound holds or all three are in: the
+            # maximum of three is never below the samples already drawn
+            e_noise = 0.0
+            for s in range(3):
+                rn = oracle.rgf(*args, extras=True, pivot_noise=1000 + e + 100000 * s)
+                Tn = oracle.transmission(rn["row0"][wl.l - 1], wl.sigma_L[e], wl.sigma_R[e])
+                e_noise = max(e_noise, rel(rn["G"], ref), abs(Tn - Tref) / max(1.0, abs(Tref)))
+                tol = max(TOL, 2.0 * e_noise)
+                if err <= tol and terr <= tol:
+                    break
+        print(f"energy {e}: |dG|/|G| {err:.2e}, dT {terr:.2e}, bound {tol:.2e}", flush=True)
         assert err <= tol, (e, err, tol)
         assert abs(T[e] - Tref) <= tol * max(1.0, abs(Tref)), (e, T[e], Tref, tol)
 
