@@ -34,7 +34,13 @@ HBM_PEAK_GBS = 8000.0
 # is stored with the figure, and a mismatch reports null.
 TRAFFIC_SOURCES = ("paper_2605_19910_amd/csrc/block_engine.h", "paper_2605_19910_amd/csrc/kernels.h",
                    "paper_2605_19910_amd/csrc/ddrgf.hip", "paper_2605_19910_amd/csrc/rgf_sweep.hip")
-MEASURED_TRAFFIC = {}
+MEASURED_TRAFFIC = {
+    # DDRGF interior kernel, l=256, b=128, 64 energies, 8 domains: FETCH_SIZE 6.4352e+07 KiB x 2.00
+    # + WRITE_SIZE 5.0856e+07 KiB x 1.00 (copy calibration: 1 GiB copy reads 5.2431e+05, writes 1.0486e+06 KiB)
+    ("ddrgf_interior_kernel", "c2/ddrgf_fp64"): {
+        "sha256": "5d43c3204608ca478e8097c0d1049b20054c3daf4c7e7a09bdf4926ddfb9aa11",
+        "bytes": 1.838642e+11},
+}
 
 
 def sources_digest() -> str:
