@@ -12,6 +12,7 @@ from .rgf_oracle import (  # noqa: F401
     dense_selected,
     ddrgf,
     domain_layout,
+    grad_band,
     grad_onsite,
     gamma_of,
     nrgf,
@@ -20,4 +21,12 @@ from .rgf_oracle import (  # noqa: F401
     solve_energy,
     transmission,
     transmission_g11,
+)
+from .ext_precision import (  # noqa: F401
+    lu_factor_ext,
+    lu_solve_ext,
+    lu_solve_right_ext,
+    nrgf_ext,
+    solve_energy_ext,
+    transmission_ext,
 )

@@ -695,6 +695,35 @@ def grad_onsite(H, E, sigma_L, sigma_R, eta_d=0.0):
     return T, grad
 
 
+def grad_band(H, E, sigma_L, sigma_R, eta_d=0.0):
+    """dT/dH for every entry of every band block of a block tridiagonal H (w = 1),
+    each entry an independent complex parameter h = x + i y, in PyTorch's complex
+    convention dT/dx + i dT/dy.
+
+    M = (E + i eta_d) I - H - Sigma, so dG = G dH G and, with Gamma Hermitian,
+    dT = 2 Re Tr[Gamma_L dG_{0,l-1} Gamma_R G_{0,l-1}^H]
+       = 2 Re sum_{i,j} Tr[dH_ij Y_ij],   Y_ij = G_{j,l-1} X G_{0,i},
+    X = Gamma_R G_{0,l-1}^H Gamma_L.  For one entry (a, c) of block (i, j) this gives
+    dT/dx = 2 Re (Y_ij)_{c,a} and dT/dy = -2 Im (Y_ij)_{c,a}, i.e. the gradient block
+    dT/dH_ij = 2 Y_ij^H.  The first block row G_{0,i} and the last block column
+    G_{j,l-1} come from Algorithm 1's extras (:func:`rgf`).
+    Returns (T, band [3, l, b, b]) with blocks outside the matrix zero."""
+    res = rgf(H, E, sigma_L, sigma_R, eta_d, extras=True)
+    l, b = H.shape[1], H.shape[2]
+    G0L = res["row0"][l - 1]
+    gl, gr = gamma_of(sigma_L), gamma_of(sigma_R)
+    Xm = gr @ G0L.conj().T @ gl
+    out = np.zeros((3, l, b, b), dtype=np.complex128)
+    for i in range(l):
+        for k in (-1, 0, 1):
+            j = i + k
+            if 0 <= j < l:
+                Y = res["colL"][j] @ Xm @ res["row0"][i]
+                out[1 + k, i] = 2.0 * Y.conj().T
+    T = float(np.real(np.trace(gl @ G0L @ gr @ G0L.conj().T)))
+    return T, out
+
+
 # ----------------------------------------------------------------------------
 # Convenience: one energy of a workload through a chosen method
 # ----------------------------------------------------------------------------
