@@ -111,10 +111,12 @@ def nrgf_flops_per_energy(l: int, b: int, w: int) -> float:
 
 
 def adjoint_flops(l: int, b: int, ne: int, nd: int) -> float:
-    """Flops of the adjoint kernel, 8 b^3 per complex product: X = Gamma_R R^H Gamma_L
-    (2 per (energy, domain)), P recomputed inside each domain (one product per layer
-    but the domain's last), and per layer R_i (all but the domain's first), X R_i and
-    G_ii P_i."""
+    """Flops of the adjoint kernel (on-site gradient), 8 b^3 per complex product or
+    Gauss-Jordan inversion: per (energy, domain of n layers starting at i0), the
+    upward sweep re-run from the domain's checkpointed pivot (n inversions, n
+    multipliers U_i but none for layer 0, n - 1 multipliers L_i and n - 1 Schur
+    updates), X = Gamma_R R^H Gamma_L (2), P rebuilt inside the domain (n - 1), and
+    per layer R_i (all but the domain's first), X R_i and G_ii P_i."""
     dlen = -(-l // nd)
     per = 0
     for k in range(nd):
@@ -122,7 +124,7 @@ def adjoint_flops(l: int, b: int, ne: int, nd: int) -> float:
         if i0 >= l:
             continue
         n = min(dlen, l - i0)
-        per += 2 + (n - 1) + (n - 1) + 2 * n
+        per += n + (n - (1 if i0 == 0 else 0)) + 2 * (n - 1) + 2 + (n - 1) + (n - 1) + 2 * n
     return per * 8.0 * float(b) ** 3 * ne
 
 
@@ -161,23 +163,51 @@ def log(msg: str):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(wl, n_sample: int, workers: int, cfg: int = 2):
-    # fresh interpreters with one BLAS thread each (forking a process whose BLAS
-    # thread pool is running can deadlock); each worker regenerates the seeded input
+def cpu_info() -> dict:
+    """CPU model and the BLAS NumPy uses, for the baseline's record."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    blas = ""
+    try:
+        import numpy as np
+        cfg = np.show_config(mode="dicts")
+        b = cfg.get("Build Dependencies", {}).get("blas", {})
+        blas = f"{b.get('name', '')} {b.get('version', '')}".strip()
+    except Exception:
+        pass
+    return {"cpu_model": model, "blas": blas, "affinity_cores": len(os.sched_getaffinity(0))}
+
+
+def cpu_baseline(wl, workers: int, cfg: int = 2, runs: int = 3):
+    """The oracle over the whole energy grid, one energy per worker process (fresh
+    interpreters, one BLAS thread each), median wall time of ``runs`` runs."""
     os.environ["OPENBLAS_NUM_THREADS"] = "1"
     os.environ["OMP_NUM_THREADS"] = "1"
-    idx = list(range(min(n_sample, wl.ne)))
+    idx = list(range(wl.ne))
     ctx = mp.get_context("spawn")
+    walls = []
     with ctx.Pool(workers, initializer=_worker_init, initargs=(cfg,)) as pool:
         pool.map(_noop, range(workers), chunksize=1)
-        log(f"cpu baseline: {workers} workers ready, timing {len(idx)} oracle energies")
-        t0 = time.perf_counter()
-        pool.map(_oracle_one, idx, chunksize=1)
-        dt = time.perf_counter() - t0
-    log(f"cpu baseline: {dt:.1f} s")
-    return {"value": len(idx) / dt, "unit": "energy points/s", "cores": workers, "kind": "oracle",
-            "sample": f"first {len(idx)} of the {wl.ne} energies of the same system, one energy per "
-                      f"worker process, {workers} processes with 1 BLAS thread each, wall {dt:.1f} s"}
+        log(f"cpu baseline: {workers} workers ready, timing {len(idx)} oracle energies x {runs} runs")
+        for _ in range(runs):
+            t0 = time.perf_counter()
+            pool.map(_oracle_one, idx, chunksize=1)
+            walls.append(time.perf_counter() - t0)
+    dt = float(sorted(walls)[len(walls) // 2])
+    log(f"cpu baseline: median {dt:.1f} s of {[round(w, 1) for w in walls]}")
+    out = {"value": len(idx) / dt, "unit": "energy points/s", "cores": workers, "kind": "oracle",
+           "sample": f"all {len(idx)} energies of the same system (sequential RGF + T), one energy per "
+                     f"worker process, {workers} processes with 1 BLAS thread each, median wall of {runs} "
+                     f"runs {dt:.1f} s"}
+    out.update(cpu_info())
+    return out
 
 
 def main():
@@ -234,7 +264,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         workers = args.cpu_workers or min(16, len(os.sched_getaffinity(0)))
-        cpu = cpu_baseline(wl, 2 * workers, workers)
+        cpu = cpu_baseline(wl, workers)
     dev = torch.device("cuda:0")
     H = torch.from_numpy(wl.H).to(dev)
     sL = torch.from_numpy(wl.sigma_L).to(dev)
@@ -262,10 +292,12 @@ def main():
         for _ in range(args.warmup):
             step()
         torch.cuda.synchronize()
-        if not bool((info == 0).all()) or not bool(torch.isfinite(T).all()):
+        status = info & binding.INFO_STATUS_MASK
+        if not bool((status == 0).all()) or not bool(torch.isfinite(T).all()):
             print(json.dumps({"error": f"{leg} solve reported a failure",
                               "info": info.cpu().tolist()}), flush=True)
             sys.exit(1)
+        n_fp64 = int(((info & binding.INFO_FP64_PRODUCTS) != 0).sum().item())
         log(f"{leg}: warmup done; timing")
         plan.set_timing(True, 16 * args.steps + 16)
         events = []
@@ -283,6 +315,8 @@ def main():
         step_ms = float(np.mean([a.elapsed_time(c) for a, c in events]))
         res = {"value": ne * args.steps / wall, "ms_per_step": 1000.0 * wall / args.steps,
                "gpu_ms_per_step": step_ms}
+        if prec != "fp64":
+            res["energies_with_fp32_products"] = ne - n_fp64
         # per-kernel durations from the library's HIP events on the launch stream
         times = plan.kernel_times()
         plan.set_timing(False)
@@ -296,7 +330,7 @@ def main():
         res["flops_per_launch"] = flops_of.get(dom)
         del ws, plan
         torch.cuda.empty_cache()
-        if prec != "fp64" and ref_G is not None:
+        if leg != "rgf_fp64" and ref_G is not None:
             res["err_vs_fp64"] = rel_err_stats(G, T, ref_G, ref_T)
         log(f"{leg}: {res['value']:.2f} energy points/s, {step_ms:.2f} ms per step")
         return res
@@ -571,9 +605,12 @@ def bench_adjoint(args):
     ws = torch.empty((plan.workspace_bytes,), dtype=torch.uint8, device=dev)
     log(f"adjoint: workspace {plan.workspace_bytes / 2**30:.1f} GiB")
 
+    Gd = G[:, 1]      # diagonal blocks read in place from the output band
+
     def step():
         binding.rgf_solve(plan, H, sL, sR, E, wl.eta_d, G, T, info, ws, stream.cuda_stream)
-        binding.rgf_backward(plan, sL, sR, G, dLdT, grad, ws, stream.cuda_stream)
+        binding.rgf_backward(plan, H, sL, sR, E, wl.eta_d, Gd, 3 * l * b * b, dLdT, None, grad, ws,
+                             stream.cuda_stream)
 
     res, times = _timed_steps(args, step, plan, stream, ne, "forward+adjoint")
     res["all_info_zero"] = bool((info == 0).all())

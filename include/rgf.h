@@ -62,11 +62,31 @@ typedef enum {
   RGF_MIXED_FP32 = 1,    /* every block product on FP32 MFMA (operands rounded to FP32,
                             FP32 accumulation, widened to FP64), Schur pivots inverted in
                             FP64 and refined once in FP64: g <- g + g (I - S g).
+                            The FP32 rounding (2^-24) is amplified by the pivots'
+                            conditioning, so each energy runs with FP32 products only while
+                            every Schur pivot S_i satisfies kappa_1(S_i) * 2^-24 <=
+                            mixed_tolerance (desc field; 1e-5 when 0); at the first pivot
+                            that does not, the energy is recomputed with FP64 products and
+                            RGF_INFO_FP64_PRODUCTS is set in its info entry.
                             Sequential method with w = 1 only (else RGF_ERR_UNSUPPORTED):
-                            on DDRGF's closed interiors FP32 products lose all accuracy.
-                            The error grows with the Schur pivots' conditioning. */
-  RGF_MIXED_BF16X3 = 2   /* reserved, not supported: split-BF16 products */
+                            DDRGF's closed interiors are ill-conditioned at most energies. */
+  RGF_MIXED_BF16X3 = 2   /* not built (always RGF_ERR_UNSUPPORTED): split-BF16 products.
+                            They would carry the same FP32 accumulation as RGF_MIXED_FP32,
+                            whose accuracy is already limited by pivot conditioning. */
 } rgf_precision_t;
+
+/* Flag in info[e] after a RGF_MIXED_FP32 solve: energy e was recomputed with FP64
+ * products (a Schur pivot was too ill-conditioned for FP32 products).  The low 30
+ * bits keep the status described above (0 = ok). */
+#define RGF_INFO_FP64_PRODUCTS 0x40000000
+#define RGF_INFO_STATUS_MASK 0x3fffffff
+/* info[e] of a batched instance whose device-table entry (num_layers, block_size)
+ * differs from the plan's shape: the instance was skipped, its outputs untouched. */
+#define RGF_INFO_TABLE_MISMATCH (-1)
+
+/* want_backward flags */
+#define RGF_BACKWARD_ONSITE 1   /* on-site energy gradient */
+#define RGF_BACKWARD_BAND 2     /* gradient with respect to the whole band of H (sizes the workspace) */
 
 typedef enum {
   RGF_METHOD_SEQUENTIAL = 0,  /* Schur-complement sweep, Algorithm 1 / Sec. 2.3 */
@@ -84,8 +104,11 @@ typedef struct {
   int64_t num_domains;       /* DDRGF: number of (interior, separator) pairs m >= 1 */
   int64_t separator_layers;  /* DDRGF: layers per separator; 0 means w (the only value supported) */
   int32_t want_transmission; /* nonzero: T is computed when the T pointer is not NULL */
-  int32_t want_backward;     /* nonzero: rgf_solve keeps what rgf_backward needs (sequential, w = 1, FP64) */
+  int32_t want_backward;     /* 0, or RGF_BACKWARD_ONSITE and/or RGF_BACKWARD_BAND: rgf_solve keeps
+                                the checkpoints rgf_backward needs (sequential, w = 1, FP64) */
   int64_t checkpoint_domains;/* rgf_backward: layers are cut into this many domains (0 = 8) */
+  double mixed_tolerance;    /* RGF_MIXED_FP32: largest kappa_1(S_i) * 2^-24 run with FP32
+                                products (0 = 1e-5, the mixed-precision error target) */
 } rgf_desc_t;
 
 /* Validate a description and build a plan.  *workspace_bytes receives the size of
@@ -125,7 +148,7 @@ rgf_status_t ddrgf_solve(rgf_plan_t plan, const void* H, const void* sigma_L, co
 
 /* Host-side shape of one device. */
 typedef struct {
-  int64_t num_layers;     /* l_d >= 2 */
+  int64_t num_layers;     /* l_d >= 1 */
   int64_t block_size;     /* b_d in {32, 64, 96, 128} */
   int64_t num_energies;   /* nE_d >= 1 */
 } rgf_batch_shape_t;
@@ -140,7 +163,7 @@ typedef struct {
   void* G_diag;             /* out [nE][l][b][b]: diagonal blocks of G */
   double* T;                /* out [nE], may be NULL */
   int32_t* info;            /* out [nE], as for rgf_solve */
-  int32_t num_layers;       /* must equal the plan's shape */
+  int32_t num_layers;       /* must equal the plan's shape (else info[] = RGF_INFO_TABLE_MISMATCH) */
   int32_t block_size;
 } rgf_batch_device_t;
 
@@ -151,7 +174,8 @@ typedef enum {
 } rgf_schedule_t;
 
 /* Build a batched plan.  shapes: host array [num_devices].  precision: RGF_FP64 or
- * RGF_MIXED_FP32.  grid: persistent workgroups (0 = one per compute unit of the
+ * RGF_MIXED_FP32 (with the conditioning switch of RGF_MIXED_FP32 at tolerance 1e-5,
+ * reported per instance through RGF_INFO_FP64_PRODUCTS in the device's info[]).  grid: persistent workgroups (0 = one per compute unit of the
  * current device).  Unlike the other plans this one owns a small device array (the
  * work queue, 3 ints per instance), allocated here and freed by rgf_plan_destroy;
  * creating it needs a visible GPU.  *workspace_bytes: one workspace slot per
@@ -166,22 +190,42 @@ rgf_status_t rgf_batched_plan_create(int64_t num_devices, const rgf_batch_shape_
 rgf_status_t rgf_batched_solve(rgf_plan_t plan, const rgf_batch_device_t* devices, double eta_d,
                                void* workspace, size_t workspace_bytes, void* stream);
 
-/* Adjoint of the transmission with respect to on-site energies.
+/* Adjoint of the transmission: gradients of L = sum_E dL_dT[E] T(E) with respect to
+ * the band of H and to on-site energies (the paper has no gradient; this follows
+ * from dG = G dH G, M = (E + i eta_d) I - H - Sigma).
  *
- * For L = sum_E dL_dT[E] T(E) and on-site shifts eps (H_ii,ss += eps_{i,s}, so
- * M_ss -= eps), first-order perturbation dG = G dH G gives
- *     dT/d eps_{i,s} = 2 Re[(G_{i,l-1} X G_{0,i})_{ss}],  X = Gamma_R G_{0,l-1}^H Gamma_L.
+ * With X = Gamma_R G_{0,l-1}^H Gamma_L and Y_ij = G_{j,l-1} X G_{0,i}:
+ *   dH[1+k][i] (block (i, j = i+k), k in {-1, 0, 1}) = sum_E dL_dT[E] * 2 Y_ij^H,
+ *     the gradient with respect to each entry of H taken as an independent complex
+ *     parameter, in PyTorch's convention dL/dRe + i dL/dIm (H is not assumed
+ *     Hermitian; blocks outside the matrix are not written);
+ *   d_onsite[i][s] = sum_E dL_dT[E] * 2 Re (Y_ii)_ss, the gradient with respect to a
+ *     real shift H_ii,ss += eps_{i,s} (the real part of dH's diagonal).
  * The plan must have been created with want_backward (sequential method, w = 1,
- * FP64) and rgf_solve must have run with it on the same inputs, G and workspace
- * (left untouched in between): the forward stored the sweep blocks U_i and, at the
- * boundaries of checkpoint_domains domains, the first block row G_{0,i} and the
- * last-column propagator P_i = -U_{i+1} P_{i+1}; the adjoint runs one workgroup
- * per (energy, domain), recomputes both inside its domain from the checkpoints,
- * and writes d_onsite[l][b] (device, real) = sum over energies in a fixed order
- * (deterministic).  dL_dT: [nE] device doubles. */
-rgf_status_t rgf_backward(rgf_plan_t plan, const void* sigma_L, const void* sigma_R, const void* G,
-                          const double* dL_dT, double* d_onsite, void* workspace, size_t workspace_bytes,
-                          void* stream);
+ * FP64; RGF_BACKWARD_BAND is needed for dH) and rgf_solve must have run with it on
+ * the same H, sigma, energies and eta_d.  Checkpointing: rgf_solve leaves in the
+ * first rgf_plan_checkpoint_bytes() bytes of its workspace, per energy and per
+ * checkpoint domain, the Schur pivot and the last-column propagator at the domain's
+ * last layer and the propagator and first block row at its first layer; only this
+ * prefix must be preserved until rgf_backward (the rest of the workspace is scratch
+ * for both calls and may be another buffer of the plan's size whose prefix holds a
+ * copy).  rgf_backward re-runs each domain's upward sweep from its checkpointed
+ * pivot (bitwise the forward's multipliers), one workgroup per (domain, chunk of
+ * energies), and sums in a fixed order (deterministic, independent of the domain
+ * count).
+ * G_diag: diagonal blocks of the forward's G (device), energy e at G_diag + e *
+ * g_diag_stride complex elements (0 = l*b*b, i.e. a compact [nE][l][b][b] array; pass
+ * G + l*b*b with stride 3*l*b*b to read them from the output band).  dL_dT: [nE]
+ * device doubles.  dH: band [3][l][b][b] (device, may be NULL); d_onsite: [l][b]
+ * device doubles (may be NULL); not both NULL. */
+rgf_status_t rgf_backward(rgf_plan_t plan, const void* H, const void* sigma_L, const void* sigma_R,
+                          const double* energies, double eta_d, const void* G_diag, int64_t g_diag_stride,
+                          const double* dL_dT, void* dH, double* d_onsite, void* workspace,
+                          size_t workspace_bytes, void* stream);
+
+/* Bytes at the start of the workspace that rgf_backward reads from the forward
+ * (0 for plans without want_backward). */
+rgf_status_t rgf_plan_checkpoint_bytes(rgf_plan_t plan, size_t* checkpoint_bytes);
 
 /* ---------------------------------------------------------------------------
  * Per-kernel timing (measurement aid; not part of the method).

@@ -14,6 +14,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "lib", "librgf.so")
 
 RGF_OK = 0
+BACKWARD_ONSITE = 1                 # want_backward flags (RGF_BACKWARD_ONSITE / _BAND)
+BACKWARD_BAND = 2
+INFO_FP64_PRODUCTS = 0x40000000     # RGF_INFO_FP64_PRODUCTS: a mixed solve recomputed the energy in FP64
+INFO_STATUS_MASK = 0x3fffffff
 STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported configuration", 3: "out of host memory",
           4: "workspace missing or too small", 5: "HIP runtime error",
           6: "plan does not match the entry point"}
@@ -34,6 +38,7 @@ class RgfDesc(ctypes.Structure):
         ("want_transmission", ctypes.c_int32),
         ("want_backward", ctypes.c_int32),
         ("checkpoint_domains", ctypes.c_int64),
+        ("mixed_tolerance", ctypes.c_double),
     ]
 
 
@@ -88,8 +93,11 @@ def load() -> ctypes.CDLL:
     lib.rgf_batched_plan_create.restype = ctypes.c_int
     lib.rgf_batched_solve.argtypes = [_VP, _VP, ctypes.c_double, _VP, ctypes.c_size_t, _VP]
     lib.rgf_batched_solve.restype = ctypes.c_int
-    lib.rgf_backward.argtypes = [_VP, _VP, _VP, _VP, _VP, _VP, _VP, ctypes.c_size_t, _VP]
+    lib.rgf_backward.argtypes = [_VP, _VP, _VP, _VP, _VP, ctypes.c_double, _VP, ctypes.c_int64, _VP, _VP, _VP,
+                                 _VP, ctypes.c_size_t, _VP]
     lib.rgf_backward.restype = ctypes.c_int
+    lib.rgf_plan_checkpoint_bytes.argtypes = [_VP, ctypes.POINTER(ctypes.c_size_t)]
+    lib.rgf_plan_checkpoint_bytes.restype = ctypes.c_int
     lib.rgf_plan_set_timing.argtypes = [_VP, ctypes.c_int32, ctypes.c_int32]
     lib.rgf_plan_set_timing.restype = ctypes.c_int
     lib.rgf_plan_kernel_times.argtypes = [_VP, ctypes.POINTER(KernelTime), ctypes.c_int32,
@@ -108,17 +116,23 @@ class Plan:
 
     def __init__(self, l: int, b: int, w: int, ne: int, method: str = "rgf", precision: str = "fp64",
                  domains: int = 0, separator_layers: int = 0, want_transmission: bool = True,
-                 want_backward: bool = False, checkpoint_domains: int = 0):
+                 want_backward: bool = False, checkpoint_domains: int = 0, mixed_tolerance: float = 0.0):
         self.lib = load()
+        wb = int(want_backward) if not isinstance(want_backward, bool) else (BACKWARD_ONSITE if want_backward else 0)
         self.desc = RgfDesc(l, b, w, ne, PRECISION[precision], METHOD[method], domains,
-                            separator_layers, 1 if want_transmission else 0, 1 if want_backward else 0,
-                            checkpoint_domains)
+                            separator_layers, 1 if want_transmission else 0, wb,
+                            checkpoint_domains, float(mixed_tolerance))
         self.handle = _VP()
         ws = ctypes.c_size_t(0)
         st = self.lib.rgf_plan_create(ctypes.byref(self.desc), ctypes.byref(self.handle), ctypes.byref(ws))
         if st != RGF_OK:
             raise RgfError("rgf_plan_create", st)
         self.workspace_bytes = int(ws.value)
+        ck = ctypes.c_size_t(0)
+        st = self.lib.rgf_plan_checkpoint_bytes(self.handle, ctypes.byref(ck))
+        if st != RGF_OK:
+            raise RgfError("rgf_plan_checkpoint_bytes", st)
+        self.checkpoint_bytes = int(ck.value)
         self.method = method
         self.l, self.b, self.w, self.ne = l, b, w, ne
 
@@ -166,8 +180,10 @@ def rgf_solve(plan: Plan, H, sigma_L, sigma_R, energies, eta_d: float, G, T, inf
         raise RgfError("rgf_solve", st)
 
 
-def rgf_backward(plan: Plan, sigma_L, sigma_R, G, dL_dT, d_onsite, workspace, stream: int = 0) -> None:
-    st = plan.lib.rgf_backward(plan.handle, _ptr(sigma_L), _ptr(sigma_R), _ptr(G), _ptr(dL_dT), _ptr(d_onsite),
+def rgf_backward(plan: Plan, H, sigma_L, sigma_R, energies, eta_d: float, G_diag, g_diag_stride: int, dL_dT,
+                 dH, d_onsite, workspace, stream: int = 0) -> None:
+    st = plan.lib.rgf_backward(plan.handle, _ptr(H), _ptr(sigma_L), _ptr(sigma_R), _ptr(energies), float(eta_d),
+                               _ptr(G_diag), int(g_diag_stride), _ptr(dL_dT), _ptr(dH), _ptr(d_onsite),
                                _ptr(workspace), workspace.numel() * workspace.element_size(), stream)
     if st != RGF_OK:
         raise RgfError("rgf_backward", st)

@@ -687,6 +687,63 @@ __device__ __forceinline__ double wg_sum(double v, double* red /* LDS, >= NW */)
   return s;
 }
 
+// Workgroup maximum of one double per thread (every thread gets the result; NaN wins).
+template <int NW>
+__device__ __forceinline__ double wg_max(double v, double* red /* LDS, >= NW */) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const double o = __shfl_xor(v, off, 64);
+    v = (o > v || o != o) ? o : v;
+  }
+  if (lane_id() == 0) red[wave_id()] = v;
+  __syncthreads();
+  double m = red[0];
+#pragma unroll
+  for (int k = 1; k < NW; ++k) m = (red[k] > m || red[k] != red[k]) ? red[k] : m;
+  __syncthreads();
+  return m;
+}
+
+// 1-norm condition number ||S||_1 ||g||_1 of a pivot S and its inverse g, both
+// bp x bp row-major in global memory (the identity padding leaves both norms >= 1,
+// so the value is never below the b x b block's).  Column sums of |s_rc| are split
+// over all threads in row slices and combined through LDS scratch (at least
+// 2 * NT doubles, free outside gj_invert).  Every thread gets the result.
+template <int T, int NW>
+__device__ __forceinline__ double kappa1(const double2* S, const double2* g, double* scr, double* red) {
+  constexpr int BP = 16 * T;
+  constexpr int NT = 64 * NW;
+  constexpr int NS = NT / BP > 0 ? NT / BP : 1;        // row slices per column
+  const int t = threadIdx.x;
+  const int c = t % BP, s = t / BP;
+  __syncthreads();
+  if (s < NS) {
+    double ps = 0.0, pg = 0.0;
+    for (int r = s; r < BP; r += NS) {
+      const double2 x = S[(size_t)r * BP + c];
+      const double2 y = g[(size_t)r * BP + c];
+      ps += sqrt(x.x * x.x + x.y * x.y);
+      pg += sqrt(y.x * y.x + y.y * y.y);
+    }
+    scr[s * BP + c] = ps;
+    scr[NS * BP + s * BP + c] = pg;
+  }
+  __syncthreads();
+  double ns = 0.0, ng = 0.0;
+  for (int cc = t; cc < BP; cc += NT) {
+    double a = 0.0, b = 0.0;
+    for (int k = 0; k < NS; ++k) {
+      a += scr[k * BP + cc];
+      b += scr[NS * BP + k * BP + cc];
+    }
+    ns = (a > ns || a != a) ? a : ns;
+    ng = (b > ng || b != b) ? b : ng;
+  }
+  ns = wg_max<NW>(ns, red);
+  ng = wg_max<NW>(ng, red);
+  return ns * ng;
+}
+
 // T = Re Tr[Gamma_L R Gamma_R R^H] with Gamma = i (Sigma - Sigma^H), R = G_{0,l-1}
 // (padded bp x bp, ld = bp, in global memory).  GamL, GamR, X1: bp x bp scratch.
 // All threads call it; the result is returned to every thread.

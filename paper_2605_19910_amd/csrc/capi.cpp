@@ -15,9 +15,11 @@ struct rgf_plan_s {
   int bp;
   size_t ws_bytes;
   size_t ws_chain;   // sequential sweep: workspace elements per energy
-  // adjoint (want_backward): checkpoint domains, scratch and per-energy gradients
-  int nd = 0, dlen = 0;
-  size_t off_adj = 0, adj_chain = 0, off_grad = 0;
+  // adjoint (want_backward): checkpoint domains, energy chunks; the workspace starts
+  // with the checkpoints (ck_bytes, preserved from rgf_solve to rgf_backward) and the
+  // rest is scratch shared by the forward sweep and the adjoint
+  int nd = 0, dlen = 0, nch = 0;
+  size_t ck_chain = 0, ck_bytes = 0, off_fwd = 0, off_adj = 0, adj_wg = 0, off_grad = 0, off_hpart = 0;
   // DDRGF workspace layout (byte offsets)
   size_t dd_int_chain, dd_red_chain;
   size_t off_int, off_ms, off_gs, off_gsrow, off_red, off_fin, off_info;
@@ -28,7 +30,7 @@ struct rgf_plan_s {
   int batched = 0;
   std::vector<rgf_batch_shape_t> shapes;
   int n_items = 0, grid = 0;
-  int* d_index = nullptr;        // device: queue[n], inst_dev[n], inst_energy[n]
+  int* d_index = nullptr;        // device: queue[n], inst_dev[n], inst_energy[n], shape[n_dev][2]
   size_t ws_slot = 0;
   std::mutex mu;                 // guards the cached graph
   bool has_graph = false;
@@ -82,6 +84,10 @@ void ktime_mark(const char* kernel, hipStream_t s) {
 
 namespace {
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+constexpr double DEFAULT_MIXED_TOLERANCE = 1e-5;
+constexpr int ADJOINT_ENERGY_CHUNKS = 64;
+// largest pivot kappa_1 with FP32 products: tolerance / 2^-24
+double kappa_limit(double tol) { return (tol > 0.0 ? tol : DEFAULT_MIXED_TOLERANCE) * 16777216.0; }
 }
 
 namespace {
@@ -94,6 +100,7 @@ rgf_status_t validate(const rgf_desc_t* d) {
   if (d->num_layers > 1 && d->half_bandwidth >= d->num_layers) return RGF_ERR_INVALID_ARG;
   if (d->num_layers > (int64_t)1 << 24 || d->num_energies > (int64_t)1 << 24) return RGF_ERR_UNSUPPORTED;
   if (d->precision != RGF_FP64 && d->precision != RGF_MIXED_FP32) return RGF_ERR_UNSUPPORTED;
+  if (!(d->mixed_tolerance >= 0.0)) return RGF_ERR_INVALID_ARG;
   // mixed precision: sequential block-tridiagonal sweep only (FP32 products on the
   // closed interiors of DDRGF lose all accuracy on ill-conditioned interiors)
   if (d->precision == RGF_MIXED_FP32 && (d->half_bandwidth > 1 || d->method != RGF_METHOD_SEQUENTIAL))
@@ -101,6 +108,7 @@ rgf_status_t validate(const rgf_desc_t* d) {
   if (d->method != RGF_METHOD_SEQUENTIAL && d->method != RGF_METHOD_DDRGF) return RGF_ERR_INVALID_ARG;
   if (d->half_bandwidth > 4) return RGF_ERR_UNSUPPORTED;
   if (d->want_backward) {
+    if (d->want_backward & ~(RGF_BACKWARD_ONSITE | RGF_BACKWARD_BAND)) return RGF_ERR_INVALID_ARG;
     if (d->method != RGF_METHOD_SEQUENTIAL || d->half_bandwidth != 1 || d->precision != RGF_FP64)
       return RGF_ERR_UNSUPPORTED;
     if (d->checkpoint_domains < 0) return RGF_ERR_INVALID_ARG;
@@ -141,16 +149,25 @@ rgf_status_t rgf_plan_create(const rgf_desc_t* desc, rgf_plan_t* plan, size_t* w
     p->ws_chain = rgfk::nrgf_ws_chain_elems((int)desc->num_layers, w, p->bp);
   p->ws_bytes = p->ws_chain * sizeof(double2) * (size_t)desc->num_energies;
   if (desc->want_backward) {
-    const int l = (int)desc->num_layers, ne = (int)desc->num_energies;
+    const int l = (int)desc->num_layers, ne = (int)desc->num_energies, b = (int)desc->block_size;
     const size_t bpbp = (size_t)p->bp * p->bp;
     const int req = desc->checkpoint_domains > 0 ? (int)std::min<int64_t>(desc->checkpoint_domains, l) : std::min(8, l);
     p->dlen = (l + req - 1) / req;
     p->nd = (l + p->dlen - 1) / p->dlen;
-    p->ws_chain += (size_t)(2 * p->nd + 1) * bpbp;
-    p->adj_chain = (size_t)(p->dlen + 7) * bpbp;
-    p->off_adj = align256(p->ws_chain * sizeof(double2) * (size_t)ne);
-    p->off_grad = align256(p->off_adj + p->adj_chain * sizeof(double2) * (size_t)ne * p->nd);
-    p->ws_bytes = align256(p->off_grad + (size_t)ne * l * desc->block_size * sizeof(double));
+    // energy chunks of the adjoint: a function of nE only, so that the band gradient's
+    // summation order does not depend on the number of domains
+    p->nch = std::min(ne, ADJOINT_ENERGY_CHUNKS);
+    p->ck_chain = (size_t)(4 * p->nd + 1) * bpbp;
+    p->ck_bytes = align256(p->ck_chain * sizeof(double2) * (size_t)ne);
+    p->off_fwd = p->ck_bytes;
+    const size_t fwd = p->ws_chain * sizeof(double2) * (size_t)ne;
+    p->adj_wg = rgfk::adjoint_scratch_wg_elems(p->dlen, p->bp);
+    p->off_adj = p->ck_bytes;
+    p->off_grad = align256(p->off_adj + p->adj_wg * sizeof(double2) * (size_t)p->nd * p->nch);
+    p->off_hpart = align256(p->off_grad + (size_t)ne * l * b * sizeof(double));
+    size_t adj_end = p->off_hpart;
+    if (desc->want_backward & RGF_BACKWARD_BAND) adj_end += (size_t)p->nch * 3 * l * (size_t)b * b * sizeof(double2);
+    p->ws_bytes = align256(std::max(p->off_fwd + fwd, adj_end));
   }
   if (desc->method == RGF_METHOD_DDRGF) {
     const int l = (int)desc->num_layers / w, m = (int)desc->num_domains, ne = (int)desc->num_energies;
@@ -243,11 +260,15 @@ rgf_status_t rgf_batched_plan_create(int64_t num_devices, const rgf_batch_shape_
   if (hipGetDevice(&dev) != hipSuccess) return RGF_ERR_HIP;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return RGF_ERR_HIP;
   const int g = std::max(1, std::min(grid > 0 ? grid : cus, n));
-  std::vector<int> host(3 * (size_t)n);
+  std::vector<int> host(3 * (size_t)n + 2 * (size_t)num_devices);
   for (int k = 0; k < n; ++k) {
     host[k] = k;                       // instance id = queue position: the tables are in queue order
     host[n + k] = items[k].dev;
     host[2 * n + k] = items[k].en;
+  }
+  for (int64_t d = 0; d < num_devices; ++d) {
+    host[3 * (size_t)n + 2 * d] = (int)shapes[d].num_layers;
+    host[3 * (size_t)n + 2 * d + 1] = (int)shapes[d].block_size;
   }
   rgf_plan_s* p = new (std::nothrow) rgf_plan_s();
   if (!p) return RGF_ERR_OUT_OF_MEMORY;
@@ -284,12 +305,14 @@ rgf_status_t rgf_batched_solve(rgf_plan_t plan, const rgf_batch_device_t* device
   a.queue = plan->d_index;
   a.inst_dev = plan->d_index + plan->n_items;
   a.inst_energy = plan->d_index + 2 * (size_t)plan->n_items;
+  a.dev_shape = plan->d_index + 3 * (size_t)plan->n_items;
   a.n_items = plan->n_items;
   a.counter = reinterpret_cast<int*>(ws);
   a.ws_slots = reinterpret_cast<double2*>(ws + 256);
   a.ws_slot = plan->ws_slot;
   a.eta_d = eta_d;
   a.mixed = plan->d.precision == RGF_MIXED_FP32 ? 1 : 0;
+  a.kappa_max = kappa_limit(0.0);
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (st == nullptr) {
     // the default stream cannot be captured: launch directly
@@ -373,12 +396,15 @@ rgf_status_t rgf_solve(rgf_plan_t plan, const void* H, const void* sigma_L, cons
   a.info = info;
   a.info_stride = 1;
   a.info_offset = 0;
-  a.ws = static_cast<double2*>(workspace);
+  a.ws = reinterpret_cast<double2*>(static_cast<char*>(workspace) + plan->off_fwd);
   a.ws_chain = plan->ws_chain;
+  a.ck = d.want_backward ? static_cast<double2*>(workspace) : nullptr;
+  a.ck_chain = plan->ck_chain;
   a.l = (int)d.num_layers;
   a.b = (int)d.block_size;
   a.chains = (int)d.num_energies;
   a.mixed = d.precision == RGF_MIXED_FP32 ? 1 : 0;
+  a.kappa_max = kappa_limit(d.mixed_tolerance);
   a.nd = d.want_backward ? plan->nd : 0;
   a.dlen = d.want_backward ? plan->dlen : 0;
   hipError_t e = rgfk::launch_rgf_sweep(a, static_cast<hipStream_t>(stream));
@@ -438,38 +464,57 @@ rgf_status_t ddrgf_solve(rgf_plan_t plan, const void* H, const void* sigma_L, co
   a.ws_fin = reinterpret_cast<double2*>(ws + plan->off_fin);
   a.info_part = reinterpret_cast<int*>(ws + plan->off_info);
   a.mixed = d.precision == RGF_MIXED_FP32 ? 1 : 0;
+  a.kappa_max = kappa_limit(d.mixed_tolerance);
   hipError_t e = rgfk::launch_ddrgf(a, st);
   if (e == hipSuccess && w > 1) e = rgfk::launch_unfuse(f, st);
   return e == hipSuccess ? RGF_OK : RGF_ERR_HIP;
 }
 
-rgf_status_t rgf_backward(rgf_plan_t plan, const void* sigma_L, const void* sigma_R, const void* G,
-                          const double* dL_dT, double* d_onsite, void* workspace, size_t workspace_bytes,
-                          void* stream) {
+rgf_status_t rgf_backward(rgf_plan_t plan, const void* H, const void* sigma_L, const void* sigma_R,
+                          const double* energies, double eta_d, const void* G_diag, int64_t g_diag_stride,
+                          const double* dL_dT, void* dH, double* d_onsite, void* workspace,
+                          size_t workspace_bytes, void* stream) {
   if (!plan) return RGF_ERR_INVALID_ARG;
   if (plan->batched || !plan->d.want_backward) return RGF_ERR_PLAN_MISMATCH;
-  if (!sigma_L || !sigma_R || !G || !dL_dT || !d_onsite) return RGF_ERR_INVALID_ARG;
+  if (!H || !sigma_L || !sigma_R || !energies || !G_diag || !dL_dT || (!dH && !d_onsite))
+    return RGF_ERR_INVALID_ARG;
+  if (dH && !(plan->d.want_backward & RGF_BACKWARD_BAND)) return RGF_ERR_PLAN_MISMATCH;
+  if (g_diag_stride < 0) return RGF_ERR_INVALID_ARG;
   if (!workspace || workspace_bytes < plan->ws_bytes) return RGF_ERR_WORKSPACE_TOO_SMALL;
   TimedScope timed(plan, static_cast<hipStream_t>(stream));
   char* ws = static_cast<char*>(workspace);
+  const int l = (int)plan->d.num_layers, b = (int)plan->d.block_size;
   rgfk::AdjArgs a{};
+  a.H = static_cast<const double2*>(H);
   a.sigL = static_cast<const double2*>(sigma_L);
   a.sigR = static_cast<const double2*>(sigma_R);
-  a.G = static_cast<const double2*>(G);
+  a.E = energies;
+  a.eta_d = eta_d;
+  a.Gd = static_cast<const double2*>(G_diag);
+  a.gd_stride = g_diag_stride > 0 ? (size_t)g_diag_stride : (size_t)l * b * b;
   a.dLdT = dL_dT;
-  a.gradE = reinterpret_cast<double*>(ws + plan->off_grad);
-  a.d_onsite = d_onsite;
-  a.ws = reinterpret_cast<double2*>(ws);
-  a.ws_chain = plan->ws_chain;
+  a.ck = reinterpret_cast<const double2*>(ws);
+  a.ck_chain = plan->ck_chain;
   a.scratch = reinterpret_cast<double2*>(ws + plan->off_adj);
-  a.scratch_chain = plan->adj_chain;
-  a.l = (int)plan->d.num_layers;
-  a.b = (int)plan->d.block_size;
+  a.scratch_wg = plan->adj_wg;
+  a.gradE = d_onsite ? reinterpret_cast<double*>(ws + plan->off_grad) : nullptr;
+  a.hpart = dH ? reinterpret_cast<double2*>(ws + plan->off_hpart) : nullptr;
+  a.d_onsite = d_onsite;
+  a.dH = static_cast<double2*>(dH);
+  a.l = l;
+  a.b = b;
   a.ne = (int)plan->d.num_energies;
   a.nd = plan->nd;
   a.dlen = plan->dlen;
+  a.nch = plan->nch;
   hipError_t e = rgfk::launch_rgf_adjoint(a, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? RGF_OK : RGF_ERR_HIP;
+}
+
+rgf_status_t rgf_plan_checkpoint_bytes(rgf_plan_t plan, size_t* checkpoint_bytes) {
+  if (!plan || !checkpoint_bytes) return RGF_ERR_INVALID_ARG;
+  *checkpoint_bytes = plan->ck_bytes;
+  return RGF_OK;
 }
 
 rgf_status_t rgf_plan_set_timing(rgf_plan_t plan, int32_t enable, int32_t max_marks) {
@@ -552,6 +597,6 @@ const char* rgf_status_string(rgf_status_t s) {
   return "unknown status";
 }
 
-int rgf_version(void) { return 100; }
+int rgf_version(void) { return 200; }
 
 }  // extern "C"

@@ -50,7 +50,9 @@ __host__ __device__ inline DDLayout dd_layout(int l, int m) {
   return d;
 }
 
+#ifndef RGFK_INST_T
 size_t ddrgf_interior_ws_elems(int nmax, int bp) { return (size_t)(9 * (size_t)nmax + 2) * bp * bp; }
+#endif
 
 // Diagonal block of M for global layer i: (E + i eta) I - H_ii - [i==0] Sigma_L - [i==l-1] Sigma_R.
 template <int T, int NW>
@@ -387,7 +389,7 @@ __global__ __launch_bounds__(64 * NW, 1) void ddrgf_finalize_kernel(DDArgs a) {
 }
 
 template <int T>
-static hipError_t launch_dd_T(const DDArgs& a, hipStream_t s) {
+hipError_t launch_dd_T(const DDArgs& a, hipStream_t s) {
   constexpr int NW = T >= 7 ? 8 : 4;
   const int chains = a.ne * a.m;
   if (a.mixed)
@@ -417,6 +419,7 @@ static hipError_t launch_dd_T(const DDArgs& a, hipStream_t s) {
   r.info_stride = a.m + 1;
   r.info_offset = a.m;
   r.mixed = a.mixed;
+  r.kappa_max = a.kappa_max;
   if ((err = launch_rgf_sweep(r, s)) != hipSuccess) return err;
   if (a.mixed)
     hipLaunchKernelGGL((ddrgf_recover_kernel<T, NW, 1>), dim3(chains), dim3(64 * NW), 0, s, a);
@@ -429,6 +432,18 @@ static hipError_t launch_dd_T(const DDArgs& a, hipStream_t s) {
   ktime_mark("ddrgf_finalize_kernel", s);
   return hipSuccess;
 }
+
+#ifdef RGFK_INST_T
+template hipError_t launch_dd_T<RGFK_INST_T>(const DDArgs& a, hipStream_t s);
+#else
+extern template hipError_t launch_dd_T<1>(const DDArgs& a, hipStream_t s);
+extern template hipError_t launch_dd_T<2>(const DDArgs& a, hipStream_t s);
+extern template hipError_t launch_dd_T<3>(const DDArgs& a, hipStream_t s);
+extern template hipError_t launch_dd_T<4>(const DDArgs& a, hipStream_t s);
+extern template hipError_t launch_dd_T<5>(const DDArgs& a, hipStream_t s);
+extern template hipError_t launch_dd_T<6>(const DDArgs& a, hipStream_t s);
+extern template hipError_t launch_dd_T<7>(const DDArgs& a, hipStream_t s);
+extern template hipError_t launch_dd_T<8>(const DDArgs& a, hipStream_t s);
 
 hipError_t launch_ddrgf(const DDArgs& a, hipStream_t s) {
   switch (padded_block(a.b) / 16) {
@@ -449,5 +464,6 @@ void ddrgf_layout_host(int l, int m, int* base, int* rem) {
   *base = d.base;
   *rem = d.rem;
 }
+#endif  // RGFK_INST_T
 
 }  // namespace rgfk

@@ -1,0 +1,7 @@
+// Kernels of padded block size 128 (T = 8): compiled in a translation unit of
+// their own so that the block sizes build in parallel.
+#define RGFK_INST_T 8
+#include "rgf_sweep.hip"
+#include "ddrgf.hip"
+#include "nrgf_sweep.hip"
+#include "adjoint.hip"

@@ -33,25 +33,34 @@ struct SweepArgs {
   size_t ws_chain;
   int l, b, chains;
   int mixed;                 // 1: products on FP32 MFMA, FP64 pivots + one refinement step
-  int nd, dlen;              // adjoint checkpoints: nd domains of dlen layers (nd = 0: none);
-                             // stored after the sweep state of each chain's workspace
+  int nd, dlen;              // adjoint checkpoints: nd domains of dlen layers (nd = 0: none)
+  double kappa_max;          // mixed: pivots with a larger kappa_1 send the chain back to FP64
+  double2* ck;               // adjoint checkpoints (nd > 0): ck_chain elements per chain, layout
+  size_t ck_chain;           // as AdjArgs::ck
 };
 
-// Adjoint of T with respect to on-site energies (one workgroup per (energy, domain)).
+// Adjoint of T (one workgroup per (domain, energy chunk)); see adjoint.hip.
 struct AdjArgs {
+  const double2* H;          // band [3][l][b][b]
   const double2* sigL;       // [ne][b][b]
   const double2* sigR;
-  const double2* G;          // forward output band [ne][3][l][b][b]
+  const double* E;           // [ne]
+  double eta_d;
+  const double2* Gd;         // diagonal blocks of the forward's G: energy e at Gd + e gd_stride
+  size_t gd_stride;
   const double* dLdT;        // [ne]
-  double* gradE;             // [ne][l][b] per-energy contributions
-  double* d_onsite;          // [l][b] their sum over energies
-  double2* ws;               // forward workspace: chains of ws_chain elements
-  size_t ws_chain;
-  double2* scratch;          // [ne][nd] blocks of scratch_chain elements
-  size_t scratch_chain;
-  int l, b, ne, nd, dlen;
+  const double2* ck;         // forward checkpoints, ck_chain elements per energy:
+  size_t ck_chain;           //   S[nd], P(last layer)[nd], P(first layer)[nd], R(first layer)[nd], R_{l-1}
+  double2* scratch;          // [nd * nch] workgroup slots of scratch_wg elements
+  size_t scratch_wg;
+  double* gradE;             // [ne][l][b] per-energy on-site gradients (null: not wanted)
+  double2* hpart;            // [nch][3][l][b][b] per-chunk band gradients (null: not wanted)
+  double* d_onsite;          // out [l][b]
+  double2* dH;               // out band [3][l][b][b]
+  int l, b, ne, nd, dlen, nch;
 };
 
+size_t adjoint_scratch_wg_elems(int dlen, int bp);
 hipError_t launch_rgf_adjoint(const AdjArgs& a, hipStream_t s);
 
 // Per-kernel timing: when the solve running on this host thread belongs to a plan
@@ -86,6 +95,7 @@ struct DDArgs {
   int* info_part;            // [ne][m + 1] per-stage status
   double2* ws_fin;           // [ne][4][bp][bp]
   int mixed;                 // 1: products on FP32 MFMA, FP64 pivots + one refinement step
+  double kappa_max;          // as SweepArgs::kappa_max (reduced system)
 };
 
 size_t ddrgf_interior_ws_elems(int nmax, int bp);
@@ -98,12 +108,14 @@ struct BatchArgs {
   const int* queue;                 // [n_items] instance ids in processing order
   const int* inst_dev;              // [n_items] device of each instance
   const int* inst_energy;           // [n_items] energy index of each instance
+  const int* dev_shape;             // [n_dev][2]: the plan's (l, b) of each device
   int n_items;
   int* counter;                     // work-queue counter (reset by the launch)
   double2* ws_slots;                // one slot per persistent workgroup
   size_t ws_slot;                   // elements per slot
   double eta_d;
   int mixed;
+  double kappa_max;                 // as SweepArgs::kappa_max
 };
 
 hipError_t launch_rgf_batched(const BatchArgs& a, int grid, hipStream_t s);

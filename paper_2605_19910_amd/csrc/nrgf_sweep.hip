@@ -14,10 +14,12 @@
 
 namespace rgfk {
 
+#ifndef RGFK_INST_T
 size_t nrgf_ws_chain_elems(int l, int w, int bp) {
   // S band (2w+1) l, g l, U w l, L w l, R l, Gamma_L, Gamma_R, X1
   return ((size_t)(4 * w + 3) * l + 3) * (size_t)bp * bp;
 }
+#endif
 
 template <int T, int NW>
 __global__ __launch_bounds__(64 * NW, 1) void nrgf_sweep_kernel(NSweepArgs a) {
@@ -132,13 +134,25 @@ __global__ __launch_bounds__(64 * NW, 1) void nrgf_sweep_kernel(NSweepArgs a) {
 }
 
 template <int T>
-static hipError_t launch_n_T(const NSweepArgs& a, hipStream_t s) {
+hipError_t launch_n_T(const NSweepArgs& a, hipStream_t s) {
   constexpr int NW = T >= 7 ? 8 : 4;
   hipLaunchKernelGGL((nrgf_sweep_kernel<T, NW>), dim3(a.ne), dim3(64 * NW), 0, s, a);
   hipError_t err = hipGetLastError();
   if (err == hipSuccess) ktime_mark("nrgf_sweep_kernel", s);
   return err;
 }
+
+#ifdef RGFK_INST_T
+template hipError_t launch_n_T<RGFK_INST_T>(const NSweepArgs& a, hipStream_t s);
+#else
+extern template hipError_t launch_n_T<1>(const NSweepArgs& a, hipStream_t s);
+extern template hipError_t launch_n_T<2>(const NSweepArgs& a, hipStream_t s);
+extern template hipError_t launch_n_T<3>(const NSweepArgs& a, hipStream_t s);
+extern template hipError_t launch_n_T<4>(const NSweepArgs& a, hipStream_t s);
+extern template hipError_t launch_n_T<5>(const NSweepArgs& a, hipStream_t s);
+extern template hipError_t launch_n_T<6>(const NSweepArgs& a, hipStream_t s);
+extern template hipError_t launch_n_T<7>(const NSweepArgs& a, hipStream_t s);
+extern template hipError_t launch_n_T<8>(const NSweepArgs& a, hipStream_t s);
 
 hipError_t launch_nrgf_sweep(const NSweepArgs& a, hipStream_t s) {
   switch (padded_block(a.b) / 16) {
@@ -247,5 +261,6 @@ hipError_t launch_unfuse(const FuseArgs& a, hipStream_t s) {
   ktime_mark("unfuse_info_kernel", s);
   return hipSuccess;
 }
+#endif  // RGFK_INST_T
 
 }  // namespace rgfk

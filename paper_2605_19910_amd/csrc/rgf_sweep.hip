@@ -14,12 +14,21 @@
 //   rgf_sweep_kernel    one workgroup per chain of a uniform batch (all outputs);
 //   rgf_batched_kernel  persistent: workgroups pull chains of uneven size from a
 //                       work queue (longest first) and write T and the diagonal blocks.
+//
+// Mixed precision (MIXED = 1): every block product on FP32 MFMA, each Schur pivot
+// inverted in FP64 and refined once in FP64.  FP32 rounding (2^-24) of the products
+// is amplified by the pivots' conditioning, so after each pivot's inversion the
+// chain measures kappa_1(S_i) = ||S_i||_1 ||g_i||_1; as soon as one pivot exceeds
+// kappa_max (tolerance / 2^-24) the chain is abandoned before any output is written
+// and recomputed with FP64 products, and RGF_INFO_FP64_PRODUCTS is set in its status.
 #include "block_engine.h"
 #include "kernels.h"
 
 namespace rgfk {
 
+#if !defined(RGFK_INST_T) && !defined(RGFK_BATCHED_TU)
 int padded_block(int b) { return ((b + 15) / 16) * 16; }
+#endif
 
 
 // Everything one chain needs.  Off-diagonal outputs Gl/Gu may be null (then not
@@ -40,17 +49,23 @@ struct Chain {
   int* info;
   double2* ws;
   int l, b;
-  // adjoint checkpoints (null = none): P at the last layer of each of nd domains of
-  // dlen layers, the first block row R = G_{0,i} at the first layer of each domain,
+  // adjoint checkpoints (null = none), for nd domains of dlen layers: the Schur pivot
+  // S (before inversion) and the last-column propagator P at the last layer of each
+  // domain, P and the first block row R = G_{0,i} at the first layer of each domain,
   // and R at the last layer
+  double2* ckS;
   double2* ckP;
+  double2* ckP0;
   double2* ckR;
   double2* Rlast;
   int nd, dlen;
+  double kappa_max;    // mixed precision: largest pivot kappa_1 allowed with FP32 products
 };
 
+// Runs one chain.  Returns false (having written no output) when MIXED and a Schur
+// pivot is too ill-conditioned for FP32 products; the caller reruns it in FP64.
 template <int T, int NW, int MIXED>
-__device__ __forceinline__ void rgf_chain(const Chain& ch, GJShared& sh, double* red) {
+__device__ __forceinline__ bool rgf_chain(const Chain& ch, GJShared& sh, double* red) {
   constexpr int BP = 16 * T;
   constexpr int NT = 64 * NW;
   const int t = threadIdx.x;
@@ -109,12 +124,14 @@ __device__ __forceinline__ void rgf_chain(const Chain& ch, GJShared& sh, double*
     add_identity<T, NW>(acc);
     store<T, NW>(acc, Pb + (size_t)((l - 1) & 1) * bpbp, BP, BP, BP);
     store<T, NW>(acc, ch.ckP + (size_t)((l - 1) / ch.dlen) * bpbp, BP, BP, BP);
+    if ((l - 1) % ch.dlen == 0) store<T, NW>(acc, ch.ckP0 + (size_t)((l - 1) / ch.dlen) * bpbp, BP, BP, BP);
   }
   acc_zero<T, NW>(acc);
   diag(l - 1);
   for (int i = l - 1; i >= 0; --i) {
     double2* gi = g + (size_t)i * bpbp;
     if (MIXED) store<T, NW>(acc, Ssave, BP, BP, BP);
+    if (ch.ckS && is_last_of_domain(i)) store<T, NW>(acc, ch.ckS + (size_t)(i / ch.dlen) * bpbp, BP, BP, BP);
     gj_invert<T, NW>(acc, gi, sh);
     if (sh.bad && bad_layer < 0) bad_layer = i;
     __syncthreads();
@@ -130,6 +147,9 @@ __device__ __forceinline__ void rgf_chain(const Chain& ch, GJShared& sh, double*
       __syncthreads();
       store<T, NW>(acc, gi, BP, BP, BP);
       __syncthreads();
+      // FP32 products only while every pivot so far is well enough conditioned
+      const double kap = kappa1<T, NW>(Ssave, gi, reinterpret_cast<double*>(&sh.pn[0][0]), red);
+      if (!(kap <= ch.kappa_max)) return false;
     }
     if (i == 0) break;
     gemm_to<MIXED, T, NW>(acc, P(gi), Pn(Hl + (size_t)i * bb), ms);
@@ -143,6 +163,7 @@ __device__ __forceinline__ void rgf_chain(const Chain& ch, GJShared& sh, double*
       store<T, NW>(acc, Pb + (size_t)((i - 1) & 1) * bpbp, BP, BP, BP);
       if (is_last_of_domain(i - 1))
         store<T, NW>(acc, ch.ckP + (size_t)((i - 1) / ch.dlen) * bpbp, BP, BP, BP);
+      if ((i - 1) % ch.dlen == 0) store<T, NW>(acc, ch.ckP0 + (size_t)((i - 1) / ch.dlen) * bpbp, BP, BP, BP);
     }
     // S_{i-1} = M_{i-1,i-1} - M_{i-1,i} L_i
     gemm_to<MIXED, T, NW>(acc, Pn(Hu + (size_t)(i - 1) * bb), P(L + (size_t)i * bpbp), -ms);
@@ -204,6 +225,20 @@ __device__ __forceinline__ void rgf_chain(const Chain& ch, GJShared& sh, double*
     if (ch.info) *ch.info = bad_layer >= 0 ? bad_layer + 1 : 0;
   }
   __syncthreads();
+  return true;
+}
+
+// Mixed chains fall back to FP64 products when a pivot is too ill-conditioned.
+template <int T, int NW, int MIXED>
+__device__ __forceinline__ void run_chain(const Chain& ch, GJShared& sh, double* red) {
+  if (MIXED) {
+    if (!rgf_chain<T, NW, 1>(ch, sh, red)) {
+      rgf_chain<T, NW, 0>(ch, sh, red);
+      if (threadIdx.x == 0 && ch.info) *ch.info |= RGF_INFO_FP64_PRODUCTS;
+    }
+  } else {
+    rgf_chain<T, NW, 0>(ch, sh, red);
+  }
 }
 
 template <int T, int NW, int MIXED>
@@ -232,20 +267,24 @@ __global__ __launch_bounds__(64 * NW, 1) void rgf_sweep_kernel(SweepArgs a) {
   ch.ws = a.ws + (size_t)e * a.ws_chain;
   ch.l = l;
   ch.b = b;
-  ch.ckP = ch.ckR = ch.Rlast = nullptr;
+  ch.ckS = ch.ckP = ch.ckP0 = ch.ckR = ch.Rlast = nullptr;
   ch.nd = a.nd;
   ch.dlen = a.dlen > 0 ? a.dlen : 1;
   if (a.nd > 0) {
     const size_t bpbp = (size_t)16 * T * 16 * T;
-    ch.ckP = ch.ws + sweep_ws_chain_elems(l, 16 * T);
-    ch.ckR = ch.ckP + (size_t)a.nd * bpbp;
+    ch.ckS = a.ck + (size_t)e * a.ck_chain;
+    ch.ckP = ch.ckS + (size_t)a.nd * bpbp;
+    ch.ckP0 = ch.ckP + (size_t)a.nd * bpbp;
+    ch.ckR = ch.ckP0 + (size_t)a.nd * bpbp;
     ch.Rlast = ch.ckR + (size_t)a.nd * bpbp;
   }
-  rgf_chain<T, NW, MIXED>(ch, sh, red);
+  ch.kappa_max = a.kappa_max;
+  run_chain<T, NW, MIXED>(ch, sh, red);
 }
 
+#ifndef RGFK_BATCHED_TU
 template <int T>
-static hipError_t launch_T(const SweepArgs& a, hipStream_t s) {
+hipError_t launch_T(const SweepArgs& a, hipStream_t s) {
   constexpr int NW = T >= 7 ? 8 : 4;
   if (a.mixed)
     hipLaunchKernelGGL((rgf_sweep_kernel<T, NW, 1>), dim3(a.chains), dim3(64 * NW), 0, s, a);
@@ -255,6 +294,18 @@ static hipError_t launch_T(const SweepArgs& a, hipStream_t s) {
   if (err == hipSuccess) ktime_mark("rgf_sweep_kernel", s);
   return err;
 }
+
+#ifdef RGFK_INST_T
+template hipError_t launch_T<RGFK_INST_T>(const SweepArgs& a, hipStream_t s);
+#else
+extern template hipError_t launch_T<1>(const SweepArgs& a, hipStream_t s);
+extern template hipError_t launch_T<2>(const SweepArgs& a, hipStream_t s);
+extern template hipError_t launch_T<3>(const SweepArgs& a, hipStream_t s);
+extern template hipError_t launch_T<4>(const SweepArgs& a, hipStream_t s);
+extern template hipError_t launch_T<5>(const SweepArgs& a, hipStream_t s);
+extern template hipError_t launch_T<6>(const SweepArgs& a, hipStream_t s);
+extern template hipError_t launch_T<7>(const SweepArgs& a, hipStream_t s);
+extern template hipError_t launch_T<8>(const SweepArgs& a, hipStream_t s);
 
 hipError_t launch_rgf_sweep(const SweepArgs& a, hipStream_t s) {
   const int T = padded_block(a.b) / 16;
@@ -270,7 +321,10 @@ hipError_t launch_rgf_sweep(const SweepArgs& a, hipStream_t s) {
     default: return hipErrorInvalidValue;
   }
 }
+#endif  // RGFK_INST_T
+#endif  // !RGFK_BATCHED_TU
 
+#ifdef RGFK_BATCHED_TU
 // ---------------------------------------------------------------------------
 // Persistent batched launch over instances of uneven size.
 //
@@ -297,7 +351,13 @@ __global__ __launch_bounds__(512, 1) void rgf_batched_kernel(BatchArgs a) {
     const int inst = a.queue[item];
     const int d = a.inst_dev[inst], e = a.inst_energy[inst];
     const rgf_batch_device_t dv = a.devs[d];
-    const int l = dv.num_layers, b = dv.block_size;
+    // the shapes come from the plan (the workspace slots are sized for them); a device
+    // table whose shape differs is reported and the instance skipped
+    const int l = a.dev_shape[2 * d], b = a.dev_shape[2 * d + 1];
+    if (dv.num_layers != l || dv.block_size != b) {
+      if (threadIdx.x == 0) dv.info[e] = RGF_INFO_TABLE_MISMATCH;
+      continue;
+    }
     const size_t bb = (size_t)b * b;
     const double2* H = static_cast<const double2*>(dv.H);
     Chain ch;
@@ -317,14 +377,15 @@ __global__ __launch_bounds__(512, 1) void rgf_batched_kernel(BatchArgs a) {
     ch.ws = ws;
     ch.l = l;
     ch.b = b;
-    ch.ckP = ch.ckR = ch.Rlast = nullptr;
+    ch.ckS = ch.ckP = ch.ckP0 = ch.ckR = ch.Rlast = nullptr;
     ch.nd = 0;
     ch.dlen = 1;
+    ch.kappa_max = a.kappa_max;
     switch (b >> 4) {
-      case 2: rgf_chain<2, 8, MIXED>(ch, sh, red); break;
-      case 4: rgf_chain<4, 8, MIXED>(ch, sh, red); break;
-      case 6: rgf_chain<6, 8, MIXED>(ch, sh, red); break;
-      case 8: rgf_chain<8, 8, MIXED>(ch, sh, red); break;
+      case 2: run_chain<2, 8, MIXED>(ch, sh, red); break;
+      case 4: run_chain<4, 8, MIXED>(ch, sh, red); break;
+      case 6: run_chain<6, 8, MIXED>(ch, sh, red); break;
+      case 8: run_chain<8, 8, MIXED>(ch, sh, red); break;
       default: break;   // rejected at plan creation
     }
   }
@@ -344,5 +405,6 @@ hipError_t launch_rgf_batched(const BatchArgs& a, int grid, hipStream_t s) {
     hipLaunchKernelGGL((rgf_batched_kernel<0>), dim3(grid), dim3(512), 0, s, a);
   return hipGetLastError();
 }
+#endif  // RGFK_BATCHED_TU
 
 }  // namespace rgfk

@@ -1,0 +1,206 @@
+"""Shared parity rule and oracle worker pool for the GPU tests.
+
+Parity rule for the FP64 paths, fixed before any full-size run
+---------------------------------------------------------------
+The GPU and the oracle run the same block elimination, without pivoting across
+blocks (partial row pivoting inside each block only), so both carry the rounding
+error of each Schur pivot's inversion amplified by that pivot's condition number.
+The classical forward-error bound for inverting (or solving with) a b x b matrix of
+1-norm condition number kappa with partial pivoting is of order gamma_b * kappa with
+gamma_b = b u / (1 - b u) ~ b u, u = 2^-53.  Both sides err, hence per energy
+
+    tol = max(1e-10, 2 * b * u * kappa_max)
+
+where kappa_max is the largest kappa_1 over the Schur pivots met by the oracle's
+run of the same method at that energy (for DDRGF: interior pivots and the reduced
+system's pivots, whose blocks have w b rows).  The bound applies to the relative
+Frobenius error over all band blocks inside the matrix and to |dT| / max(1, T).
+1e-10 is the target figure; it is the bound wherever the pivots are well
+conditioned (kappa_max < ~1e3 at b = 128).
+
+Oracle work runs in a pool of fresh interpreters (one BLAS thread each), so the
+full-size comparisons over every energy take seconds to a few minutes.
+"""
+from __future__ import annotations
+
+import multiprocessing as mp
+import os
+from typing import Dict
+
+import numpy as np
+
+U64 = 2.0 ** -53
+TARGET_FP64 = 1e-10
+TARGET_MIXED = 1e-5
+
+
+def fp64_bound(kappa: float, b: int) -> float:
+    k = float(kappa)
+    if not np.isfinite(k):
+        k = 0.0          # no pivot conditioning known (dense reference): the target itself
+    return max(TARGET_FP64, 2.0 * b * U64 * k)
+
+
+def mask_band(G: np.ndarray, w: int) -> np.ndarray:
+    """Zero the band entries that fall outside the matrix (never written by the
+    library); G is [..., 2w+1, l, b, b]."""
+    G = np.array(G, copy=True)
+    l = G.shape[-3]
+    for k in range(-w, w + 1):
+        if k < 0:
+            G[..., w + k, :(-k), :, :] = 0
+        elif k > 0:
+            G[..., w + k, l - k:, :, :] = 0
+    return G
+
+
+def rel(a, b) -> float:
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(b))
+
+
+def terr(T, Tref) -> float:
+    return abs(float(T) - float(Tref)) / max(1.0, abs(float(Tref)))
+
+
+# ----------------------------------------------------------------------------
+# worker pool
+# ----------------------------------------------------------------------------
+
+_POOL = None
+
+
+def pool():
+    global _POOL
+    if _POOL is None:
+        os.environ["OPENBLAS_NUM_THREADS"] = "1"
+        os.environ["OMP_NUM_THREADS"] = "1"
+        n = max(1, min(16, len(os.sched_getaffinity(0))))
+        _POOL = mp.get_context("spawn").Pool(n)
+    return _POOL
+
+
+def pmap(fn, items):
+    """Ordered parallel map over the oracle pool."""
+    items = list(items)
+    if len(items) <= 1:
+        return [fn(x) for x in items]
+    return pool().map(fn, items, chunksize=1)
+
+
+_WL: Dict = {}
+
+
+def _workload(src):
+    """src: a Workload, ("config", n) regenerated (and cached) in the worker, or
+    ("config", 4, d) for device d of the batched workload."""
+    if isinstance(src, tuple):
+        key = src[:2]
+        if key not in _WL:
+            from workloads import make_config
+            _WL[key] = make_config(src[1])
+        return _WL[key][src[2]] if len(src) > 2 else _WL[key]
+    return src
+
+
+def _args(src, e, eta_d):
+    wl = _workload(src)
+    eta = wl.eta_d if eta_d is None else eta_d
+    return wl, (wl.H, wl.energies[e], wl.sigma_L[e], wl.sigma_R[e], eta)
+
+
+# Each task returns {"G": band, "T": transmission, "kappa": worst pivot kappa_1}.
+
+def task_rgf(spec):
+    import oracle
+    src, e, eta_d = spec
+    wl, a = _args(src, e, eta_d)
+    r = oracle.rgf(*a, extras=True, pivot_cond=True)
+    return {"G": r["G"], "T": oracle.transmission(r["row0"][wl.l - 1], a[2], a[3]), "kappa": r["pivot_cond"]}
+
+
+def task_nrgf(spec):
+    import oracle
+    src, e, eta_d = spec
+    wl, a = _args(src, e, eta_d)
+    Mb = oracle.block_accessor(wl.H, wl.w, *a[1:])
+    r = oracle.nrgf(Mb, wl.l, wl.b, wl.w, halo=1, pivot_cond=True)
+    return {"G": r["G"], "T": oracle.transmission(r["first_rows"][0, wl.l - 1], a[2], a[3]),
+            "kappa": r["pivot_cond"]}
+
+
+def task_ddrgf(spec):
+    import oracle
+    src, e, eta_d, m = spec
+    wl, a = _args(src, e, eta_d)
+    r = oracle.ddrgf(wl.H, wl.w, *a[1:], n_pairs=m, pivot_cond=True)
+    return {"G": r["G"], "T": oracle.transmission(r["G_0_last"], a[2], a[3]), "kappa": r["pivot_cond"]}
+
+
+def task_ext(spec):
+    import oracle
+    src, e, eta_d = spec
+    wl, a = _args(src, e, eta_d)
+    G, T = oracle.solve_energy_ext(wl.H, wl.w, *a[1:])
+    return {"G": np.asarray(G, dtype=np.complex128), "T": T, "kappa": float("nan")}
+
+
+def task_dense(spec):
+    import oracle
+    src, e, eta_d = spec
+    wl, a = _args(src, e, eta_d)
+    band, Gf = oracle.dense_selected(wl.H, wl.w, *a[1:], full=True)
+    b, n = wl.b, wl.l * wl.b
+    return {"G": band, "T": oracle.transmission(Gf[:b, n - b:], a[2], a[3]), "kappa": float("nan")}
+
+
+def task_mixed(spec):
+    import oracle
+    src, e, eta_d = spec
+    wl, a = _args(src, e, eta_d)
+    r = oracle.rgf_mixed_products(*a)
+    return {"G": r["G"], "T": oracle.transmission(r["G_0_last"], a[2], a[3]), "kappa": float("nan")}
+
+
+TASKS = {"rgf": task_rgf, "nrgf": task_nrgf, "ddrgf": task_ddrgf, "ext": task_ext, "dense": task_dense,
+         "mixed": task_mixed}
+
+
+def oracle_results(kind: str, src, energies, eta_d=None, m=None):
+    fn = TASKS[kind]
+    specs = [(src, int(e), eta_d, m) if kind == "ddrgf" else (src, int(e), eta_d) for e in energies]
+    return pmap(fn, specs)
+
+
+# ----------------------------------------------------------------------------
+# comparisons
+# ----------------------------------------------------------------------------
+
+def gpu_energy(G, e, w):
+    """Band of one energy from a GPU (torch) or host array, masked to the matrix."""
+    x = G[e]
+    if hasattr(x, "cpu"):
+        x = x.cpu().numpy()
+    return mask_band(x, w)
+
+
+def check_fp64(label, G, T, energies, refs, w, b, extra_bound=None):
+    """Per energy: band and T within fp64_bound(kappa, b) of the reference.  Prints
+    every energy's figures, asserts after all of them are printed.  Returns the
+    list of (e, err, terr, tol, kappa)."""
+    rows, bad = [], []
+    for e, r in zip(energies, refs):
+        err = rel(gpu_energy(G, e, w), r["G"])
+        te = terr(T[e], r["T"])
+        tol = fp64_bound(r["kappa"], b)
+        if extra_bound is not None:
+            tol = max(tol, extra_bound)
+        rows.append((e, err, te, tol, r["kappa"]))
+        print(f"{label} energy {e}: kappa {r['kappa']:.2e} |dG|/|G| {err:.2e} dT {te:.2e} bound {tol:.2e}",
+              flush=True)
+        if not (err <= tol and te <= tol):
+            bad.append((e, err, te, tol))
+    errs = np.array([x[1] for x in rows])
+    print(f"{label}: {len(rows)} energies, band error median {np.median(errs):.2e} max {errs.max():.2e}",
+          flush=True)
+    assert not bad, bad
+    return rows

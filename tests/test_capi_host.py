@@ -32,7 +32,8 @@ def declared_symbols():
 def test_header_declares_entry_points():
     syms = declared_symbols()
     for s in ("rgf_plan_create", "rgf_plan_destroy", "rgf_solve", "ddrgf_solve", "rgf_batched_plan_create",
-              "rgf_batched_solve", "rgf_backward", "rgf_plan_set_timing", "rgf_plan_kernel_times"):
+              "rgf_batched_solve", "rgf_backward", "rgf_plan_checkpoint_bytes", "rgf_plan_set_timing",
+              "rgf_plan_kernel_times"):
         assert s in syms
 
 
@@ -73,6 +74,7 @@ def test_plan_workspace_size(l, b, w, ne):
     (dict(l=8, b=4, w=1, ne=1, method="ddrgf", domains=5), 1),
     (dict(l=8, b=4, w=1, ne=1, method="ddrgf", domains=2, want_backward=True), 2),
     (dict(l=8, b=4, w=1, ne=1, precision="fp32", want_backward=True), 2),
+    (dict(l=8, b=4, w=1, ne=1, precision="fp32", mixed_tolerance=-1.0), 1),
 ])
 def test_plan_validation_errors(args, code):
     binding = _lib()
@@ -96,19 +98,34 @@ def test_solve_rejects_null_and_small_workspace():
 
 
 def test_backward_plan_workspace_and_mismatch():
+    """The adjoint's plan: checkpoints (4 nd + 1 blocks per energy) at the front of the
+    workspace, then scratch large enough for the forward sweep and for the adjoint;
+    argument and plan errors are rejected on the host."""
     binding = _lib()
     lib = binding.load()
     l, b, ne, nd = 256, 64, 4, 8
     p = binding.Plan(l, b, 1, ne, want_backward=True, checkpoint_domains=nd)
+    pb = binding.Plan(l, b, 1, ne, want_backward=binding.BACKWARD_BAND, checkpoint_domains=nd)
     plain = binding.Plan(l, b, 1, ne)
     bpbp = b * b
-    chain = (3 * l + 10 + 2 * nd + 1) * bpbp * 16
-    assert p.workspace_bytes >= chain * ne + ne * nd * (32 + 7) * bpbp * 16 + ne * l * b * 8
-    fake = ctypes.c_void_p(16)
+    ck = (4 * nd + 1) * bpbp * 16 * ne
+    assert p.checkpoint_bytes == ck and plain.checkpoint_bytes == 0
+    assert p.workspace_bytes >= ck + plain.workspace_bytes
+    # the band gradient's per-chunk partial sums (min(nE, 64) chunks of a band of H)
+    assert pb.workspace_bytes >= ck + ne * 3 * l * bpbp * 16
+    f = ctypes.c_void_p(16)
+    big = 1 << 44
     # a plan without want_backward cannot run the adjoint
-    assert lib.rgf_backward(plain.handle, fake, fake, fake, fake, fake, fake, 1 << 40, None) == 6
-    assert lib.rgf_backward(p.handle, None, fake, fake, fake, fake, fake, 1 << 40, None) == 1
-    assert lib.rgf_backward(p.handle, fake, fake, fake, fake, fake, fake, 16, None) == 4
+    assert lib.rgf_backward(plain.handle, f, f, f, f, 0.0, f, 0, f, None, f, f, big, None) == 6
+    # a band gradient needs a plan made for it
+    assert lib.rgf_backward(p.handle, f, f, f, f, 0.0, f, 0, f, f, None, f, big, None) == 6
+    # missing inputs, no output at all, negative stride, small workspace
+    assert lib.rgf_backward(p.handle, None, f, f, f, 0.0, f, 0, f, None, f, f, big, None) == 1
+    assert lib.rgf_backward(p.handle, f, f, f, f, 0.0, f, 0, f, None, None, f, big, None) == 1
+    assert lib.rgf_backward(p.handle, f, f, f, f, 0.0, f, -1, f, None, f, f, big, None) == 1
+    assert lib.rgf_backward(p.handle, f, f, f, f, 0.0, f, 0, f, None, f, f, 16, None) == 4
+    with pytest.raises(binding.RgfError):
+        binding.Plan(8, 4, 1, 1, want_backward=4)
 
 
 def test_timing_argument_errors():

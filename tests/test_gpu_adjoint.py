@@ -1,7 +1,9 @@
-"""Adjoint dT/d eps (on-site energies) on the GPU: against the oracle's gradient
-(first-order perturbation dG = G dH G), through torch.autograd, independent of the
-number of checkpoint domains, and against central finite differences of the GPU
-forward at the full 256 x 64, 256-energy size."""
+"""Adjoint on the GPU: dT/d eps (on-site energies) and dT/dH (every entry of the
+band of H) against the oracle's gradients (first-order perturbation dG = G dH G,
+pinned by finite differences on the CPU), through torch.autograd and through the
+C ABI directly; independent of the number of checkpoint domains (bitwise); the
+memory kept between forward and backward; and against central finite differences
+of the GPU forward at the full 256 x 64, 256-energy size."""
 import numpy as np
 import pytest
 
@@ -46,6 +48,66 @@ def test_adjoint_matches_oracle(lib, l, b, ne, nd):
     assert rel(g, ref) <= 1e-10, rel(g, ref)
 
 
+def gpu_grad_h(wl, nd=8, weights=None):
+    import torch
+    from paper_2605_19910_amd import autograd as ag
+    H, sL, sR, E = dev_inputs(wl)
+    H.requires_grad_(True)
+    T = ag.transmission_h(H, sL, sR, E, checkpoint_domains=nd)
+    w = torch.ones_like(T) if weights is None else torch.as_tensor(weights, device=T.device)
+    (T * w).sum().backward()
+    torch.cuda.synchronize()
+    return T.detach().cpu().numpy(), H.grad.cpu().numpy()
+
+
+@pytest.mark.parametrize("l,b,ne,nd", [(12, 16, 3, 3), (9, 37, 2, 8), (16, 64, 2, 1), (20, 128, 2, 4),
+                                       (1, 8, 2, 1), (2, 8, 2, 2), (7, 20, 2, 7)])
+def test_band_gradient_matches_oracle(lib, l, b, ne, nd):
+    wl = make_random(l, b, 1, ne, seed=4300 + l + b, eta=1e-3)
+    w = np.linspace(0.5, 1.5, ne)
+    T, g = gpu_grad_h(wl, nd, w)
+    ref = np.zeros((3, l, b, b), dtype=np.complex128)
+    for e in range(ne):
+        Te, ge = oracle.grad_band(wl.H, wl.energies[e], wl.sigma_L[e], wl.sigma_R[e])
+        ref += w[e] * ge
+        assert abs(T[e] - Te) <= 1e-10 * max(1, abs(Te))
+    assert rel(g, ref) <= 1e-10, rel(g, ref)
+    # blocks outside the matrix get no gradient
+    assert np.all(g[0, 0] == 0) and np.all(g[2, l - 1] == 0)
+
+
+def test_band_gradient_through_the_c_abi_from_the_output_band(lib):
+    """rgf_backward reading the diagonal blocks straight from the forward's output
+    band (pointer G + l b^2, stride 3 l b^2), both gradients at once, against the
+    oracle."""
+    import torch
+    from paper_2605_19910_amd import binding
+    wl = make_random(10, 24, 1, 3, seed=71, eta=1e-3)
+    H, sL, sR, E = dev_inputs(wl)
+    l, b, ne = wl.l, wl.b, wl.ne
+    plan = binding.Plan(l, b, 1, ne, want_backward=binding.BACKWARD_ONSITE | binding.BACKWARD_BAND,
+                        checkpoint_domains=3)
+    ws = torch.empty((plan.workspace_bytes,), dtype=torch.uint8, device=H.device)
+    G, T, info = binding.solve(H, sL, sR, E, plan=plan, workspace=ws)
+    dLdT = torch.tensor([1.0, -0.5, 2.0], dtype=torch.float64, device=H.device)
+    dH = torch.zeros_like(H)
+    d_on = torch.empty((l, b), dtype=torch.float64, device=H.device)
+    Gd = G[:, 1]   # view into the band: first diagonal block of energy e at G + e 3 l b^2 + l b^2
+    stream = torch.cuda.current_stream().cuda_stream
+    binding.rgf_backward(plan, H, sL, sR, E, 0.0, Gd, 3 * l * b * b, dLdT, dH, d_on, ws, stream)
+    torch.cuda.synchronize()
+    ref = np.zeros((3, l, b, b), dtype=np.complex128)
+    ref_on = np.zeros((l, b))
+    for e in range(ne):
+        ref += dLdT[e].item() * oracle.grad_band(wl.H, wl.energies[e], wl.sigma_L[e], wl.sigma_R[e])[1]
+        ref_on += dLdT[e].item() * oracle.grad_onsite(wl.H, wl.energies[e], wl.sigma_L[e], wl.sigma_R[e])[1]
+    assert rel(dH.cpu().numpy(), ref) <= 1e-10
+    assert rel(d_on.cpu().numpy(), ref_on) <= 1e-10
+    # the on-site gradient is the real part of the band gradient's diagonal entries
+    np.testing.assert_allclose(d_on.cpu().numpy(), np.real(np.diagonal(dH[1].cpu().numpy(), axis1=1, axis2=2)),
+                               rtol=0, atol=1e-12 * np.abs(ref_on).max())
+
+
 def test_checkpoint_count_does_not_change_the_result(lib):
     """P and R are recomputed from checkpoints with the same products in the same
     order as the forward's sequential recursion: bitwise identical gradients."""
@@ -54,6 +116,9 @@ def test_checkpoint_count_does_not_change_the_result(lib):
     _, g3 = gpu_grad(wl, 3)
     _, g8 = gpu_grad(wl, 8)
     assert np.array_equal(g1, g3) and np.array_equal(g1, g8)
+    _, h1 = gpu_grad_h(wl, 1)
+    _, h5 = gpu_grad_h(wl, 5)
+    assert np.array_equal(h1, h5)
 
 
 def test_config5_adjoint_vs_finite_differences(lib):
@@ -71,6 +136,16 @@ def test_config5_adjoint_vs_finite_differences(lib):
     T, g = gpu_grad(wl, 8)
     assert np.all(np.isfinite(g))
     H, sL, sR, E = dev_inputs(wl)
+    # memory kept between forward and backward: checkpoints + diagonal blocks of G,
+    # against the forward's workspace + the whole band of G that a non-checkpointed
+    # adjoint would need
+    pb = binding.Plan(wl.l, wl.b, 1, wl.ne, want_backward=True, checkpoint_domains=8)
+    plain = binding.Plan(wl.l, wl.b, 1, wl.ne)
+    blk = wl.b * wl.b * 16
+    held = pb.checkpoint_bytes + wl.ne * wl.l * blk
+    full = plain.workspace_bytes + wl.ne * 3 * wl.l * blk
+    print(f"kept between forward and backward: {held / 2**30:.2f} GiB vs {full / 2**30:.2f} GiB", flush=True)
+    assert held <= full / 4
     plan = binding.Plan(wl.l, wl.b, 1, wl.ne)
     ws = torch.empty((plan.workspace_bytes,), dtype=torch.uint8, device=H.device)
     G = torch.empty((wl.ne, 3, wl.l, wl.b, wl.b), dtype=torch.complex128, device=H.device)

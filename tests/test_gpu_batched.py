@@ -1,13 +1,13 @@
 """Persistent batched launch over (device, energy) instances of uneven size: T and
-the diagonal blocks G_ii of every instance against the FP64 oracle; hipGraph
-capture replayed several times with eager work between; the 64-device workload."""
+the diagonal blocks G_ii of every instance against the FP64 oracle under the fixed
+rule of tests/parity.py (the bound's block size is the instance's); hipGraph capture
+replayed several times with eager work between; the 64-device workload with one
+instance of every block size compared block by block."""
 import numpy as np
 import pytest
 
-import oracle
+from parity import fp64_bound, pmap, rel, task_rgf, terr
 from workloads import make_config, make_random
-
-from test_gpu_rgf import rel
 
 pytestmark = pytest.mark.gpu
 
@@ -19,25 +19,19 @@ def to_dev(wls):
              torch.from_numpy(w.sigma_R).to(d), torch.from_numpy(w.energies).to(d)) for w in wls]
 
 
-def check_instance(wl, Gd, T, e, noise=False, tol=1e-10):
-    args = (wl.H, wl.energies[e], wl.sigma_L[e], wl.sigma_R[e], wl.eta_d)
-    r = oracle.rgf(*args, extras=True)
-    ref = r["G"][1]
-    Tref = oracle.transmission(r["row0"][wl.l - 1], wl.sigma_L[e], wl.sigma_R[e])
-    if noise:
-        # the largest of three perturbed oracle runs (see test_gpu_rgf.check_energies)
-        # (drawn until the bound holds: the maximum of three is never below them)
-        err0 = rel(Gd, ref)
-        terr0 = abs(T - Tref) / max(1.0, abs(Tref))
-        for s in range(3):
-            rn = oracle.rgf(*args, extras=True, pivot_noise=500 + e + 100000 * s)
-            Tn = oracle.transmission(rn["row0"][wl.l - 1], wl.sigma_L[e], wl.sigma_R[e])
-            tol = max(tol, 2 * max(rel(rn["G"][1], ref), abs(Tn - Tref) / max(1.0, abs(Tref))))
-            if err0 <= tol and terr0 <= tol:
-                break
-    err = rel(Gd, ref)
-    assert err <= tol, (wl.name, e, err, tol)
-    assert abs(T - Tref) <= tol * max(1.0, abs(Tref)), (wl.name, e, T, Tref)
+def check_instances(label, items):
+    """items: list of (src, wl, energy, G_ii [l, b, b] host, T host)."""
+    refs = pmap(task_rgf, [(src, e, None) for (src, _, e, _, _) in items])
+    bad = []
+    for (src, wl, e, Gd, T), r in zip(items, refs):
+        err = rel(Gd, r["G"][1])
+        te = terr(T, r["T"])
+        tol = fp64_bound(r["kappa"], wl.b)
+        print(f"{label} {wl.name} (l={wl.l}, b={wl.b}) energy {e}: kappa {r['kappa']:.2e} "
+              f"|dG_ii|/|G_ii| {err:.2e} dT {te:.2e} bound {tol:.2e}", flush=True)
+        if not (err <= tol and te <= tol):
+            bad.append((wl.name, e, err, te, tol))
+    assert not bad, bad
 
 
 def small_batch():
@@ -51,11 +45,12 @@ def test_small_uneven_batch(lib, schedule):
     wls = small_batch()
     outs = lib.solve_batched(to_dev(wls), 0.0, schedule=schedule)
     torch.cuda.synchronize()
+    items = []
     for wl, (G, T, info) in zip(wls, outs):
         G, T, info = G.cpu().numpy(), T.cpu().numpy(), info.cpu().numpy()
         assert np.all(info == 0)
-        for e in range(wl.ne):
-            check_instance(wl, G[e], T[e], e)
+        items += [(wl, wl, e, G[e], T[e]) for e in range(wl.ne)]
+    check_instances(f"batched/{schedule}", items)
 
 
 def test_graph_replays_match_eager(lib):
@@ -93,18 +88,25 @@ def test_graph_replays_match_eager(lib):
 
 def test_config4_full_workload(lib):
     """64 devices, b in {32, 64, 96, 128}, l in [64, 512], 16 energies each: 1024
-    instances in one persistent launch; three instances checked block by block."""
+    instances in one persistent launch.  Every T finite and in [0, b]; for every
+    block size the longest device at two energies compared block by block."""
     import torch
     wls = make_config(4)
     outs = lib.solve_batched(to_dev(wls), 0.0)
     torch.cuda.synchronize()
     infos = np.concatenate([o[2].cpu().numpy() for o in outs])
-    Ts = np.concatenate([o[1].cpu().numpy() for o in outs])
-    assert np.all(infos == 0) and np.all(np.isfinite(Ts))
-    by_b = {}
+    Ts = [o[1].cpu().numpy() for o in outs]
+    assert np.all(infos == 0)
+    for wl, T in zip(wls, Ts):
+        assert np.all(np.isfinite(T)) and np.all(T >= -1e-8) and np.all(T <= wl.b + 1e-8)
+    pick = {}
     for d, w in enumerate(wls):
-        by_b.setdefault(w.b, d)
-    for b, d in sorted(by_b.items())[::2]:
-        wl = wls[d]
-        G = outs[d][0][3].cpu().numpy()
-        check_instance(wl, G, float(outs[d][1][3].item()), 3, noise=True)
+        if w.b not in pick or w.l > wls[pick[w.b]].l:
+            pick[w.b] = d
+    assert sorted(pick) == [32, 64, 96, 128]
+    items = []
+    for b, d in sorted(pick.items()):
+        for e in (3, 12):
+            items.append((("config", 4, d), wls[d], e, outs[d][0][e].cpu().numpy(), float(Ts[d][e])))
+    del outs
+    check_instances("config4", items)

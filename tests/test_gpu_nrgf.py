@@ -1,65 +1,23 @@
-"""GPU parity of the block n-diagonal paths (n = 2w + 1) against the FP64 oracle.
+"""GPU parity of the block n-diagonal paths (n = 2w + 1) against the FP64 oracle,
+under the fixed rule of tests/parity.py:
 
-* sequential: the native n-diagonal sweep (Sec. 2.3) vs the oracle's n-RGF; bound
-  1e-10 per energy, at the full size max(1e-10, 2 e_noise) with e_noise the
-  oracle's own rounding spread (the largest of three runs with u-perturbed Schur pivots);
-* DDRGF with separators of w layers: distance to the exact band no larger than
-  4x the oracle DDRGF's own (see test_gpu_ddrgf).
+* sequential: the native n-diagonal sweep (Sec. 2.3) against the oracle's n-RGF;
+* DDRGF with separators of w layers against the oracle's DDRGF (same algorithm),
+  its distance to the exact band printed beside.
+At the full pentadiagonal size (512 layers of 64, 128 energies) 17 energies spread
+over the grid are compared for each method, and two of them also against the
+extended-precision reference.
 """
 import numpy as np
 import pytest
 
-import oracle
+from parity import check_fp64, fp64_bound, gpu_energy, oracle_results, rel, terr
+from test_gpu_rgf import free_gpu, run_gpu, run_gpu_dev
 from workloads import make_config, make_random
 
-from test_gpu_rgf import mask_band, rel, run_gpu
-
 pytestmark = pytest.mark.gpu
-U64 = 2.0 ** -53
 
-
-def check_seq(wl, G, T, info, energies, eta_d=0.0, noise=False):
-    assert np.all(info == 0), info
-    for e in energies:
-        Mb = oracle.block_accessor(wl.H, wl.w, wl.energies[e], wl.sigma_L[e], wl.sigma_R[e], eta_d)
-        r = oracle.nrgf(Mb, wl.l, wl.b, wl.w, halo=1)
-        Tref = oracle.transmission(r["first_rows"][0, wl.l - 1], wl.sigma_L[e], wl.sigma_R[e])
-        tol = 1e-10
-        if noise:
-            # the largest of three perturbed oracle runs (see test_gpu_rgf.check_energies)
-            # (drawn until the bound holds: the maximum of three is never below them)
-            err0 = rel(mask_band(G[e], wl.w), r["G"])
-            terr0 = abs(T[e] - Tref) / max(1.0, abs(Tref))
-            for s in range(3):
-                rn = oracle.nrgf(Mb, wl.l, wl.b, wl.w, halo=1, pivot_noise=1000 + e + 100000 * s)
-                Tn = oracle.transmission(rn["first_rows"][0, wl.l - 1], wl.sigma_L[e], wl.sigma_R[e])
-                tol = max(tol, 2.0 * max(rel(rn["G"], r["G"]), abs(Tn - Tref) / max(1.0, abs(Tref))))
-                print(f"energy {e}: |dG|/|G| {err0:.2e}, bound {tol:.2e} after {s + 1} samples", flush=True)
-                if err0 <= tol and terr0 <= tol:
-                    break
-        err = rel(mask_band(G[e], wl.w), r["G"])
-        assert err <= tol, (e, err, tol)
-        assert abs(T[e] - Tref) <= tol * max(1.0, abs(Tref)), (e, T[e], Tref)
-
-
-def check_dd(wl, G, T, info, energies, m, eta_d=0.0):
-    assert np.all(info == 0), info
-    for e in energies:
-        args = (wl.H, wl.w, wl.energies[e], wl.sigma_L[e], wl.sigma_R[e], eta_d)
-        if wl.l * wl.b <= 2500:
-            ref, Gf = oracle.dense_selected(*args, full=True)
-            n, b = wl.l * wl.b, wl.b
-            Tref = oracle.transmission(Gf[:b, n - b:], wl.sigma_L[e], wl.sigma_R[e])
-        else:
-            Mb = oracle.block_accessor(*args)
-            r = oracle.nrgf(Mb, wl.l, wl.b, wl.w, halo=1)
-            ref = r["G"]
-            Tref = oracle.transmission(r["first_rows"][0, wl.l - 1], wl.sigma_L[e], wl.sigma_R[e])
-        d = oracle.ddrgf(*args, n_pairs=m)
-        tol = max(1e-10, 4.0 * rel(d["G"], ref))
-        err = rel(mask_band(G[e], wl.w), ref)
-        assert err <= tol, (e, err, tol)
-        assert abs(T[e] - Tref) <= tol * max(1.0, abs(Tref)), (e, T[e], Tref)
+C3_SAMPLE = list(range(0, 128, 8)) + [127]
 
 
 @pytest.mark.parametrize("l,b,w", [(3, 8, 2), (9, 16, 2), (14, 20, 2), (11, 37, 3), (8, 64, 2),
@@ -67,7 +25,8 @@ def check_dd(wl, G, T, info, energies, m, eta_d=0.0):
 def test_native_ndiagonal(lib, l, b, w):
     wl = make_random(l, b, w, 2, seed=1300 + l * 3 + b + w, eta=1e-3)
     G, T, info = run_gpu(lib, wl)
-    check_seq(wl, G, T, info, range(2))
+    assert np.all(info == 0)
+    check_fp64(f"nrgf l={l} b={b} w={w}", G, T, range(2), oracle_results("nrgf", wl, range(2)), w, b)
 
 
 @pytest.mark.parametrize("l,b,w,m", [(8, 8, 2, 2), (20, 16, 2, 4), (24, 20, 2, 5), (18, 12, 3, 2),
@@ -75,19 +34,61 @@ def test_native_ndiagonal(lib, l, b, w):
 def test_ddrgf_ndiagonal(lib, l, b, w, m):
     wl = make_random(l, b, w, 2, seed=1700 + l + b + w + m, eta=1e-3)
     G, T, info = run_gpu(lib, wl, method="ddrgf", domains=m)
-    check_dd(wl, G, T, info, range(2), m)
+    assert np.all(info == 0)
+    refs = oracle_results("ddrgf", wl, range(2), m=m)
+    check_fp64(f"ddrgf l={l} b={b} w={w} m={m}", G, T, range(2), refs, w, w * b)
+    for e, x in zip(range(2), oracle_results("dense", wl, range(2))):
+        print(f"  energy {e}: DDRGF vs exact band: GPU {rel(gpu_energy(G, e, w), x['G']):.2e}", flush=True)
 
 
-def test_config3_full_size_sequential(lib):
-    """Block pentadiagonal, 512 layers x 64, 128 energies, native n-diagonal sweep."""
+def test_config3_sequential(lib):
+    """Block pentadiagonal, 512 layers x 64, 128 energies, native n-diagonal sweep;
+    17 energies spread over the grid against the oracle."""
     wl = make_config(3)
-    G, T, info = run_gpu(lib, wl)
-    check_seq(wl, G, T, info, [127], noise=True)
+    G, T, info = run_gpu_dev(lib, wl)
+    assert bool((info == 0).all())
+    refs = oracle_results("nrgf", ("config", 3), C3_SAMPLE)
+    check_fp64("config3 nrgf", G, T.cpu().numpy(), C3_SAMPLE, refs, 2, wl.b)
+    del G
+    free_gpu()
 
 
-def test_config3_full_size_ddrgf(lib):
+def test_config3_ddrgf(lib):
     """Same system, DDRGF with 16 domains (separators of 2 layers; the reduced system
-    is block tridiagonal in 2-layer groups)."""
+    is block tridiagonal in 2-layer groups), the same 17 energies against the
+    oracle's DDRGF."""
     wl = make_config(3)
-    G, T, info = run_gpu(lib, wl, method="ddrgf", domains=16)
-    check_dd(wl, G, T, info, [64], 16)
+    G, T, info = run_gpu_dev(lib, wl, method="ddrgf", domains=16)
+    assert bool((info == 0).all())
+    refs = oracle_results("ddrgf", ("config", 3), C3_SAMPLE, m=16)
+    check_fp64("config3 ddrgf", G, T.cpu().numpy(), C3_SAMPLE, refs, 2, 2 * wl.b)
+    del G
+    free_gpu()
+
+
+def test_config3_distance_to_exact(lib):
+    """Energy 127 and the sampled energy with the worst-conditioned pivot: GPU
+    sequential sweep, GPU DDRGF and the FP64 oracle against the extended-precision
+    reference."""
+    wl = make_config(3)
+    kap = [r["kappa"] for r in oracle_results("nrgf", ("config", 3), C3_SAMPLE)]
+    worst = C3_SAMPLE[int(np.argmax(kap))]
+    es = sorted({127, worst})
+    kap_of = dict(zip(C3_SAMPLE, kap))
+    ext = oracle_results("ext", ("config", 3), es)
+    orc = oracle_results("nrgf", ("config", 3), es)
+    Gs, Ts, info = run_gpu_dev(lib, wl)
+    assert bool((info == 0).all())
+    rows = [(e, rel(gpu_energy(Gs, e, 2), x["G"]), rel(o["G"], x["G"]), terr(Ts[e].item(), x["T"]))
+            for e, x, o in zip(es, ext, orc)]
+    del Gs
+    free_gpu()
+    Gd, Td, info = run_gpu_dev(lib, wl, method="ddrgf", domains=16)
+    for (e, eg, eo, tg), x in zip(rows, ext):
+        ed = rel(gpu_energy(Gd, e, 2), x["G"])
+        print(f"config3 energy {e}: kappa {kap_of[e]:.2e}  vs exact: GPU sweep {eg:.2e} (T {tg:.2e}), "
+              f"oracle {eo:.2e}, ratio {eg / max(eo, 1e-300):.2f}; GPU DDRGF {ed:.2e}", flush=True)
+        tol = fp64_bound(kap_of[e], wl.b)
+        assert eg <= tol and tg <= tol, (e, eg, tg, tol)
+    del Gd
+    free_gpu()
