@@ -80,9 +80,6 @@ typedef enum {
  * bits keep the status described above (0 = ok). */
 #define RGF_INFO_FP64_PRODUCTS 0x40000000
 #define RGF_INFO_STATUS_MASK 0x3fffffff
-/* info[e] of a batched instance whose device-table entry (num_layers, block_size)
- * differs from the plan's shape: the instance was skipped, its outputs untouched. */
-#define RGF_INFO_TABLE_MISMATCH (-1)
 
 /* want_backward flags */
 #define RGF_BACKWARD_ONSITE 1   /* on-site energy gradient */
@@ -138,7 +135,7 @@ rgf_status_t ddrgf_solve(rgf_plan_t plan, const void* H, const void* sigma_L, co
  * Batched launch over systems ("devices") of uneven size
  * ---------------------------------------------------------------------------
  * Each device d has its own block-tridiagonal band H_d (l_d layers of b_d orbitals,
- * b_d in {32, 64, 96, 128}) and its own energies; one instance = one (device,
+ * b_d a multiple of 16 up to 128) and its own energies; one instance = one (device,
  * energy) pair.  All instances run in ONE persistent kernel: workgroups pull
  * instances from a work queue ordered by the plan's schedule and run the whole
  * sweep of each (Algorithm 1); the outputs are T(E) and the diagonal blocks G_ii
@@ -149,7 +146,7 @@ rgf_status_t ddrgf_solve(rgf_plan_t plan, const void* H, const void* sigma_L, co
 /* Host-side shape of one device. */
 typedef struct {
   int64_t num_layers;     /* l_d >= 1 */
-  int64_t block_size;     /* b_d in {32, 64, 96, 128} */
+  int64_t block_size;     /* b_d a multiple of 16 in [16, 128] */
   int64_t num_energies;   /* nE_d >= 1 */
 } rgf_batch_shape_t;
 
@@ -163,7 +160,7 @@ typedef struct {
   void* G_diag;             /* out [nE][l][b][b]: diagonal blocks of G */
   double* T;                /* out [nE], may be NULL */
   int32_t* info;            /* out [nE], as for rgf_solve */
-  int32_t num_layers;       /* must equal the plan's shape (else info[] = RGF_INFO_TABLE_MISMATCH) */
+  int32_t num_layers;       /* informational: the kernel takes each device's shape from the plan */
   int32_t block_size;
 } rgf_batch_device_t;
 
@@ -175,13 +172,19 @@ typedef enum {
 
 /* Build a batched plan.  shapes: host array [num_devices].  precision: RGF_FP64 or
  * RGF_MIXED_FP32 (with the conditioning switch of RGF_MIXED_FP32 at tolerance 1e-5,
- * reported per instance through RGF_INFO_FP64_PRODUCTS in the device's info[]).  grid: persistent workgroups (0 = one per compute unit of the
- * current device).  Unlike the other plans this one owns a small device array (the
- * work queue, 3 ints per instance), allocated here and freed by rgf_plan_destroy;
- * creating it needs a visible GPU.  *workspace_bytes: one workspace slot per
- * persistent workgroup, sized for the largest device, plus the queue counter. */
+ * reported per instance through RGF_INFO_FP64_PRODUCTS in the device's info[]).
+ * schedule: order of the work queue (rgf_schedule_t).  The tile: waves = wave64s
+ * per persistent workgroup, 8 (one workgroup per compute unit; 0 means 8) or 4 (two
+ * per compute unit, for batches of small blocks); grid = persistent workgroups (0 =
+ * one per compute unit of the current device for 8 waves, two for 4).  The
+ * schedule, grid and waves of a workload are what the autotuner chooses (the
+ * Python binding reads its table).  Unlike the other plans this one owns a small
+ * device array (the work queue, 3 ints per instance, and the shapes), allocated
+ * here and freed by rgf_plan_destroy; creating it needs a visible GPU.
+ * *workspace_bytes: one workspace slot per persistent workgroup, sized for the
+ * largest device, plus the queue counter. */
 rgf_status_t rgf_batched_plan_create(int64_t num_devices, const rgf_batch_shape_t* shapes,
-                                     int32_t precision, int32_t schedule, int32_t grid,
+                                     int32_t precision, int32_t schedule, int32_t grid, int32_t waves,
                                      rgf_plan_t* plan, size_t* workspace_bytes);
 
 /* Run every instance of the plan.  devices: DEVICE array [num_devices] of table
@@ -226,6 +229,9 @@ rgf_status_t rgf_backward(rgf_plan_t plan, const void* H, const void* sigma_L, c
 /* Bytes at the start of the workspace that rgf_backward reads from the forward
  * (0 for plans without want_backward). */
 rgf_status_t rgf_plan_checkpoint_bytes(rgf_plan_t plan, size_t* checkpoint_bytes);
+
+/* Workspace size of a plan (the value rgf_plan_create returned). */
+rgf_status_t rgf_plan_workspace_bytes(rgf_plan_t plan, size_t* workspace_bytes);
 
 /* ---------------------------------------------------------------------------
  * Per-kernel timing (measurement aid; not part of the method).

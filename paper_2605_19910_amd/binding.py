@@ -88,7 +88,7 @@ def load() -> ctypes.CDLL:
         f.argtypes = list(_SOLVE_ARGS)
         f.restype = ctypes.c_int
     lib.rgf_batched_plan_create.argtypes = [ctypes.c_int64, ctypes.POINTER(BatchShape), ctypes.c_int32,
-                                            ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(_VP),
+                                            ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(_VP),
                                             ctypes.POINTER(ctypes.c_size_t)]
     lib.rgf_batched_plan_create.restype = ctypes.c_int
     lib.rgf_batched_solve.argtypes = [_VP, _VP, ctypes.c_double, _VP, ctypes.c_size_t, _VP]
@@ -98,6 +98,8 @@ def load() -> ctypes.CDLL:
     lib.rgf_backward.restype = ctypes.c_int
     lib.rgf_plan_checkpoint_bytes.argtypes = [_VP, ctypes.POINTER(ctypes.c_size_t)]
     lib.rgf_plan_checkpoint_bytes.restype = ctypes.c_int
+    lib.rgf_plan_workspace_bytes.argtypes = [_VP, ctypes.POINTER(ctypes.c_size_t)]
+    lib.rgf_plan_workspace_bytes.restype = ctypes.c_int
     lib.rgf_plan_set_timing.argtypes = [_VP, ctypes.c_int32, ctypes.c_int32]
     lib.rgf_plan_set_timing.restype = ctypes.c_int
     lib.rgf_plan_kernel_times.argtypes = [_VP, ctypes.POINTER(KernelTime), ctypes.c_int32,
@@ -240,20 +242,31 @@ def solve(H, sigma_L, sigma_R, energies, eta_d: float = 0.0, method: str = "rgf"
 # ----------------------------------------------------------------------------
 
 class BatchedPlan:
-    """Owning wrapper of a batched rgf_plan_t (rgf_batched_plan_create)."""
+    """Owning wrapper of a batched rgf_plan_t (rgf_batched_plan_create).
 
-    def __init__(self, shapes, precision: str = "fp64", schedule: str = "longest_first", grid: int = 0):
+    schedule="auto" takes the queue order, grid and waves per workgroup that the
+    autotuner stored for this workload (block-size histogram, precision) and the
+    defaults (longest first, one workgroup of 8 waves per compute unit) when it has
+    not tuned it."""
+
+    def __init__(self, shapes, precision: str = "fp64", schedule: str = "longest_first", grid: int = 0,
+                 waves: int = 0):
         self.lib = load()
+        if schedule == "auto":
+            from . import autotune
+            rec = autotune.lookup(shapes, precision)
+            schedule, grid, waves = ((rec["schedule"], rec["grid"], rec.get("waves", 8)) if rec
+                                     else ("longest_first", 0, 0))
         arr = (BatchShape * len(shapes))(*[BatchShape(int(l), int(b), int(ne)) for (l, b, ne) in shapes])
         self.handle = _VP()
         ws = ctypes.c_size_t(0)
         st = self.lib.rgf_batched_plan_create(len(shapes), arr, PRECISION[precision], SCHEDULE[schedule],
-                                              int(grid), ctypes.byref(self.handle), ctypes.byref(ws))
+                                              int(grid), int(waves), ctypes.byref(self.handle), ctypes.byref(ws))
         if st != RGF_OK:
             raise RgfError("rgf_batched_plan_create", st)
         self.workspace_bytes = int(ws.value)
         self.shapes = [tuple(int(v) for v in sh) for sh in shapes]
-        self.precision, self.schedule, self.grid = precision, schedule, grid
+        self.precision, self.schedule, self.grid, self.waves = precision, schedule, grid, waves
 
     def close(self):
         if self.handle:
@@ -289,7 +302,7 @@ def rgf_batched_solve(plan: BatchedPlan, table, eta_d: float, workspace, stream:
 
 
 def solve_batched(systems, eta_d: float = 0.0, precision: str = "fp64", schedule: str = "longest_first",
-                  grid: int = 0, plan: Optional[BatchedPlan] = None, stream=None):
+                  grid: int = 0, plan: Optional[BatchedPlan] = None, stream=None, waves: int = 0):
     """systems: list of (H [3, l, b, b], sigma_L [nE, b, b], sigma_R, energies [nE]) GPU tensors.
     Runs every (system, energy) instance in one persistent launch; returns a list of
     (G_diag [nE, l, b, b], T [nE], info [nE]) per system."""
@@ -297,7 +310,7 @@ def solve_batched(systems, eta_d: float = 0.0, precision: str = "fp64", schedule
     dev = systems[0][0].device
     shapes = [(H.shape[1], H.shape[2], E.shape[0]) for (H, _, _, E) in systems]
     if plan is None:
-        plan = BatchedPlan(shapes, precision=precision, schedule=schedule, grid=grid)
+        plan = BatchedPlan(shapes, precision=precision, schedule=schedule, grid=grid, waves=waves)
     outs, entries = [], []
     for (H, sL, sR, E) in systems:
         l, b, ne = H.shape[1], H.shape[2], E.shape[0]

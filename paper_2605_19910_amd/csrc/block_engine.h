@@ -263,6 +263,33 @@ __device__ __forceinline__ void store(const Acc<T, NW>& acc, double2* p, int ld,
   }
 }
 
+// Write (sgn * acc)^H into p: element (i, j) of acc goes to p[j*ld + i], conjugated,
+// for j < nr, i < nc (nr x nc is the shape of the destination).
+template <int T, int NW>
+__device__ __forceinline__ void store_conjT(const Acc<T, NW>& acc, double2* p, int ld, int nr, int nc,
+                                            double sgn = 1.0) {
+  constexpr int RR = Acc<T, NW>::RR;
+  constexpr int RC = Acc<T, NW>::RC;
+  const int l = lane_id();
+  int tr0, tc0;
+  tile_origin<T, NW>(tr0, tc0);
+#pragma unroll
+  for (int r = 0; r < RR; ++r) {
+    if (tr0 + r >= T) continue;
+#pragma unroll
+    for (int c = 0; c < RC; ++c) {
+      if (tc0 + c >= T) continue;
+      const int j = 16 * (tc0 + c) + c_col(l);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 16 * (tr0 + r) + c_row(l, v);
+        if (j < nr && i < nc)
+          p[(size_t)j * ld + i] = make_double2(sgn * acc.re[r][c][v], -sgn * acc.im[r][c][v]);
+      }
+    }
+  }
+}
+
 // Load a block (read through an operand view) into acc.
 template <int T, int NW>
 __device__ __forceinline__ void load(Acc<T, NW>& acc, const Opnd& X, double sgn = 1.0) {

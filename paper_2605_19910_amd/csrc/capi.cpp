@@ -22,14 +22,14 @@ struct rgf_plan_s {
   size_t ck_chain = 0, ck_bytes = 0, off_fwd = 0, off_adj = 0, adj_wg = 0, off_grad = 0, off_hpart = 0;
   // DDRGF workspace layout (byte offsets)
   size_t dd_int_chain, dd_red_chain;
-  size_t off_int, off_ms, off_gs, off_gsrow, off_red, off_fin, off_info;
+  size_t off_int, off_ms, off_gs, off_gsrow, off_red, off_fin, off_info, off_herm;
   // w > 1 DDRGF: super-block copies of the inputs and of the output band
   int fl, fb;                    // super-layers and super-block size of the DDRGF system
   size_t off_hf, off_slf, off_srf, off_gf, off_inff;
   // batched plans
   int batched = 0;
   std::vector<rgf_batch_shape_t> shapes;
-  int n_items = 0, grid = 0;
+  int n_items = 0, grid = 0, waves = 8;
   int* d_index = nullptr;        // device: queue[n], inst_dev[n], inst_energy[n], shape[n_dev][2]
   size_t ws_slot = 0;
   std::mutex mu;                 // guards the cached graph
@@ -188,6 +188,7 @@ rgf_status_t rgf_plan_create(const rgf_desc_t* desc, rgf_plan_t* plan, size_t* w
     p->off_red = off;   off = align256(off + p->dd_red_chain * sizeof(double2) * (size_t)ne);
     p->off_fin = off;   off = align256(off + (size_t)ne * 4 * bpbp * sizeof(double2));
     p->off_info = off;  off = align256(off + (size_t)ne * (m + 1) * sizeof(int));
+    p->off_herm = off;  off = align256(off + sizeof(int));
     if (w > 1) {
       p->off_hf = off;   off = align256(off + (size_t)3 * l * bb * sizeof(double2));
       p->off_slf = off;  off = align256(off + (size_t)ne * bb * sizeof(double2));
@@ -215,13 +216,14 @@ rgf_status_t rgf_plan_destroy(rgf_plan_t plan) {
 }
 
 rgf_status_t rgf_batched_plan_create(int64_t num_devices, const rgf_batch_shape_t* shapes,
-                                     int32_t precision, int32_t schedule, int32_t grid,
+                                     int32_t precision, int32_t schedule, int32_t grid, int32_t waves,
                                      rgf_plan_t* plan, size_t* workspace_bytes) {
   if (!plan) return RGF_ERR_INVALID_ARG;
   *plan = nullptr;
   if (num_devices < 1 || num_devices > (1 << 20) || !shapes) return RGF_ERR_INVALID_ARG;
   if (precision != RGF_FP64 && precision != RGF_MIXED_FP32) return RGF_ERR_UNSUPPORTED;
   if (schedule < 0 || schedule > 2 || grid < 0) return RGF_ERR_INVALID_ARG;
+  if (waves != 0 && waves != 4 && waves != 8) return RGF_ERR_INVALID_ARG;
   struct Item { int dev, en; double cost; int b; };
   std::vector<Item> items;
   size_t slot = 0;
@@ -229,8 +231,7 @@ rgf_status_t rgf_batched_plan_create(int64_t num_devices, const rgf_batch_shape_
     const rgf_batch_shape_t& sh = shapes[d];
     if (sh.num_layers < 1 || sh.num_layers > (1 << 20) || sh.num_energies < 1 || sh.num_energies > (1 << 20))
       return RGF_ERR_INVALID_ARG;
-    if (sh.block_size != 32 && sh.block_size != 64 && sh.block_size != 96 && sh.block_size != 128)
-      return RGF_ERR_UNSUPPORTED;
+    if (sh.block_size < 16 || sh.block_size > 128 || sh.block_size % 16 != 0) return RGF_ERR_UNSUPPORTED;
     slot = std::max(slot, rgfk::sweep_ws_chain_elems((int)sh.num_layers, (int)sh.block_size));
     const double cost = (double)sh.num_layers * (double)sh.block_size * sh.block_size * sh.block_size;
     for (int64_t e = 0; e < sh.num_energies; ++e) items.push_back({(int)d, (int)e, cost, (int)sh.block_size});
@@ -240,15 +241,15 @@ rgf_status_t rgf_batched_plan_create(int64_t num_devices, const rgf_batch_shape_
     std::stable_sort(items.begin(), items.end(), [](const Item& x, const Item& y) { return x.cost > y.cost; });
   } else if (schedule == RGF_SCHEDULE_INTERLEAVED) {
     // longest first inside each block size, then take one from each size in turn
-    std::vector<std::vector<Item>> by(4);
-    for (const Item& it : items) by[it.b / 32 - 1].push_back(it);
+    std::vector<std::vector<Item>> by(8);
+    for (const Item& it : items) by[it.b / 16 - 1].push_back(it);
     for (auto& v : by)
       std::stable_sort(v.begin(), v.end(), [](const Item& x, const Item& y) { return x.cost > y.cost; });
-    std::vector<size_t> pos(4, 0);
+    std::vector<size_t> pos(8, 0);
     items.clear();
     for (bool more = true; more;) {
       more = false;
-      for (int c = 3; c >= 0; --c)
+      for (int c = 7; c >= 0; --c)
         if (pos[c] < by[c].size()) {
           items.push_back(by[c][pos[c]++]);
           more = true;
@@ -277,7 +278,8 @@ rgf_status_t rgf_batched_plan_create(int64_t num_devices, const rgf_batch_shape_
   p->d.precision = precision;
   p->shapes.assign(shapes, shapes + num_devices);
   p->n_items = n;
-  p->grid = g;
+  p->waves = waves == 0 ? 8 : waves;
+  p->grid = waves == 4 && grid == 0 ? std::max(1, std::min(2 * cus, n)) : g;
   p->ws_slot = slot;
   if (hipMalloc(&p->d_index, host.size() * sizeof(int)) != hipSuccess) {
     delete p;
@@ -316,7 +318,7 @@ rgf_status_t rgf_batched_solve(rgf_plan_t plan, const rgf_batch_device_t* device
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (st == nullptr) {
     // the default stream cannot be captured: launch directly
-    return rgfk::launch_rgf_batched(a, plan->grid, st) == hipSuccess ? RGF_OK : RGF_ERR_HIP;
+    return rgfk::launch_rgf_batched(a, plan->grid, plan->waves, st) == hipSuccess ? RGF_OK : RGF_ERR_HIP;
   }
   std::lock_guard<std::mutex> lock(plan->mu);
   const bool same = plan->has_graph && plan->g_devs == devices && plan->g_ws == workspace &&
@@ -328,9 +330,9 @@ rgf_status_t rgf_batched_solve(rgf_plan_t plan, const rgf_batch_device_t* device
       plan->has_graph = false;
     }
     if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
-      return rgfk::launch_rgf_batched(a, plan->grid, st) == hipSuccess ? RGF_OK : RGF_ERR_HIP;
+      return rgfk::launch_rgf_batched(a, plan->grid, plan->waves, st) == hipSuccess ? RGF_OK : RGF_ERR_HIP;
     }
-    hipError_t le = rgfk::launch_rgf_batched(a, plan->grid, st);
+    hipError_t le = rgfk::launch_rgf_batched(a, plan->grid, plan->waves, st);
     hipGraph_t graph = nullptr;
     hipError_t ce = hipStreamEndCapture(st, &graph);
     if (le != hipSuccess || ce != hipSuccess) {
@@ -463,6 +465,7 @@ rgf_status_t ddrgf_solve(rgf_plan_t plan, const void* H, const void* sigma_L, co
   a.ws_red_chain = plan->dd_red_chain;
   a.ws_fin = reinterpret_cast<double2*>(ws + plan->off_fin);
   a.info_part = reinterpret_cast<int*>(ws + plan->off_info);
+  a.herm = reinterpret_cast<int*>(ws + plan->off_herm);
   a.mixed = d.precision == RGF_MIXED_FP32 ? 1 : 0;
   a.kappa_max = kappa_limit(d.mixed_tolerance);
   hipError_t e = rgfk::launch_ddrgf(a, st);
@@ -509,6 +512,12 @@ rgf_status_t rgf_backward(rgf_plan_t plan, const void* H, const void* sigma_L, c
   a.nch = plan->nch;
   hipError_t e = rgfk::launch_rgf_adjoint(a, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? RGF_OK : RGF_ERR_HIP;
+}
+
+rgf_status_t rgf_plan_workspace_bytes(rgf_plan_t plan, size_t* workspace_bytes) {
+  if (!plan || !workspace_bytes) return RGF_ERR_INVALID_ARG;
+  *workspace_bytes = plan->ws_bytes;
+  return RGF_OK;
 }
 
 rgf_status_t rgf_plan_checkpoint_bytes(rgf_plan_t plan, size_t* checkpoint_bytes) {

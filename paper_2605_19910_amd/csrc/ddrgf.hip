@@ -52,6 +52,33 @@ __host__ __device__ inline DDLayout dd_layout(int l, int m) {
 
 #ifndef RGFK_INST_T
 size_t ddrgf_interior_ws_elems(int nmax, int bp) { return (size_t)(9 * (size_t)nmax + 2) * bp * bp; }
+
+__global__ void herm_flag_init_kernel(int* flag) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *flag = 1;
+}
+
+// Clears *flag unless the band of H is exactly Hermitian: H_ii = H_ii^H and
+// H_{i+1,i} = H_{i,i+1}^H entry by entry (NaN entries count as a mismatch).
+__global__ void herm_check_kernel(const double2* H, int l, int b, int* flag) {
+  const size_t bb = (size_t)b * b;
+  const size_t total = (size_t)2 * l * bb;
+  for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const int c = (int)(idx % b), r = (int)((idx / b) % b);
+    const int i = (int)((idx / bb) % l);
+    const bool diag = idx < (size_t)l * bb;
+    double2 x, y;
+    if (diag) {
+      x = H[((size_t)l + i) * bb + (size_t)r * b + c];
+      y = H[((size_t)l + i) * bb + (size_t)c * b + r];
+    } else {
+      if (i + 1 >= l) continue;
+      x = H[(size_t)(i + 1) * bb + (size_t)r * b + c];              // block (i+1, i)
+      y = H[((size_t)2 * l + i) * bb + (size_t)c * b + r];          // block (i, i+1), transposed
+    }
+    if (!(x.x == y.x && x.y == -y.y)) *flag = 0;
+  }
+}
 #endif
 
 // Diagonal block of M for global layer i: (E + i eta) I - H_ii - [i==0] Sigma_L - [i==l-1] Sigma_R.
@@ -76,10 +103,8 @@ __device__ __forceinline__ const double2* Hup(const DDArgs& a, int i) {
 // 1. interiors
 // ---------------------------------------------------------------------------
 template <int T, int NW, int MIXED>
-__global__ __launch_bounds__(64 * NW, 1) void ddrgf_interior_kernel(DDArgs a) {
+__device__ __forceinline__ void interior_general(const DDArgs& a, int c, GJShared& sh) {
   constexpr int BP = 16 * T;
-  __shared__ GJShared sh;
-  const int c = blockIdx.x;
   const int e = c / a.m, k = c % a.m;
   const DDLayout lay = dd_layout(a.l, a.m);
   const int n = lay.n(k), a0 = lay.a(k), qR = lay.p(k), qL = a0 - 1;
@@ -200,6 +225,112 @@ __global__ __launch_bounds__(64 * NW, 1) void ddrgf_interior_kernel(DDArgs a) {
   if (threadIdx.x == 0) a.info_part[(size_t)e * (a.m + 1) + k] = bad_layer >= 0 ? bad_layer + 1 : 0;
 }
 
+// Closed interior with a Hermitian matrix (H Hermitian, no lead in the interior,
+// eta_d = 0, E real): X = M_D^{-1} is Hermitian, U_i = L_i^H, Q_i = P_i^H,
+// X_{i-1,i} = X_{i,i-1}^H, and the halo products RL = CL^H, RR = CR^H, so per layer
+// the upward pass forms L_i, P_{i-1} = -L_i^H P_i and the Schur update, and the
+// downward pass X_{i,i-1}, X_ii, CL_i, CR_i: 7 products instead of 12.  RL and RR
+// are not stored; the recovery reads CL^H and CR^H.
+template <int T, int NW, int MIXED>
+__device__ __forceinline__ void interior_herm(const DDArgs& a, int c, GJShared& sh) {
+  constexpr int BP = 16 * T;
+  const int e = c / a.m, k = c % a.m;
+  const DDLayout lay = dd_layout(a.l, a.m);
+  const int n = lay.n(k), a0 = lay.a(k);
+  const int b = a.b;
+  const size_t bb = (size_t)b * b, bpbp = (size_t)BP * BP;
+  const int nmax = lay.base + 1;
+  double2* ws = a.ws_int + (size_t)c * a.ws_int_chain;
+  // the general path's layout (g, U, L, P, Q, CL, CR, RL, RR); U, Q, RL, RR unused
+  double2* g = ws;
+  double2* L = g + (size_t)2 * nmax * bpbp;
+  double2* Pt = L + (size_t)nmax * bpbp;
+  double2* CL = Pt + (size_t)2 * nmax * bpbp;
+  double2* CR = CL + (size_t)nmax * bpbp;
+  double2* Gout = a.G + (size_t)e * 3 * a.l * bb;
+  double2* Gl = Gout;
+  double2* Gd = Gout + (size_t)a.l * bb;
+  double2* Gu = Gout + (size_t)2 * a.l * bb;
+  int bad_layer = -1;
+  Acc<T, NW> acc;
+  auto P = [&](const double2* p) { return opnd(p, BP, BP, BP); };
+  auto Pb = [&](const double2* p) { return opnd(p, b, b, b); };
+
+  // ---------------- upward pass ----------------
+  diag_M<T, NW>(acc, a, e, a0 + n - 1);
+  for (int i = n - 1; i >= 0; --i) {
+    double2* gi = g + (size_t)i * bpbp;
+    gj_invert<T, NW>(acc, gi, sh);
+    if (sh.bad && bad_layer < 0) bad_layer = a0 + i;
+    __syncthreads();
+    if (i == n - 1) {
+      // P_{n-1} folded with M_{e,qR} = -H_{e,e+1}
+      load<T, NW>(acc, Pb(Hup(a, a0 + n - 1)), -1.0);
+      store<T, NW>(acc, Pt + (size_t)i * bpbp, BP, BP, BP);
+      __syncthreads();
+    }
+    if (i == 0) break;
+    const int gl = a0 + i;
+    gemm_to<MIXED, T, NW>(acc, P(gi), Pb(Hlo(a, gl)), -1.0);
+    store<T, NW>(acc, L + (size_t)i * bpbp, BP, BP, BP);
+    __syncthreads();
+    // P_{i-1} = -U_i P_i = -L_i^H P_i
+    gemm_to<MIXED, T, NW>(acc, opnd(L + (size_t)i * bpbp, BP, BP, BP, 1), P(Pt + (size_t)i * bpbp), -1.0);
+    store<T, NW>(acc, Pt + (size_t)(i - 1) * bpbp, BP, BP, BP);
+    // S_{i-1} = M_{i-1,i-1} + H_{i-1,i} L_i
+    gemm_to<MIXED, T, NW>(acc, Pb(Hup(a, gl - 1)), P(L + (size_t)i * bpbp), 1.0);
+    diag_M<T, NW>(acc, a, e, gl - 1, true);
+    __syncthreads();
+  }
+
+  // ---------------- downward pass ----------------
+  load<T, NW>(acc, P(g));
+  store<T, NW>(acc, Gd + (size_t)a0 * bb, b, b, b);
+  __syncthreads();
+  const Opnd X00 = Pb(Gd + (size_t)a0 * bb);
+  gemm_to<MIXED, T, NW>(acc, X00, Pb(Hlo(a, a0)), -1.0);            // CL_0 = X_00 M_{a,qL}
+  store<T, NW>(acc, CL, BP, BP, BP);
+  gemm_to<MIXED, T, NW>(acc, X00, P(Pt), 1.0);                      // CR_0 = X_00 P_0
+  store<T, NW>(acc, CR, BP, BP, BP);
+  __syncthreads();
+  for (int i = 1; i < n; ++i) {
+    const int gl = a0 + i;
+    const Opnd Xp = Pb(Gd + (size_t)(gl - 1) * bb);
+    const Opnd Li = P(L + (size_t)i * bpbp);
+    // X_{i,i-1} = -L_i X_{i-1,i-1};  X_{i-1,i} = X_{i,i-1}^H
+    gemm_to<MIXED, T, NW>(acc, Li, Xp, -1.0);
+    store<T, NW>(acc, Gl + (size_t)gl * bb, b, b, b);
+    store_conjT<T, NW>(acc, Gu + (size_t)(gl - 1) * bb, b, b, b);
+    gemm_to<MIXED, T, NW>(acc, Li, P(CL + (size_t)(i - 1) * bpbp), -1.0);
+    store<T, NW>(acc, CL + (size_t)i * bpbp, BP, BP, BP);
+    __syncthreads();
+    // X_ii = g_i - L_i X_{i-1,i}
+    gemm_to<MIXED, T, NW>(acc, Li, Pb(Gu + (size_t)(gl - 1) * bb), -1.0);
+    add_from<T, NW>(acc, P(g + (size_t)i * bpbp));
+    store<T, NW>(acc, Gd + (size_t)gl * bb, b, b, b);
+    __syncthreads();
+    gemm_to<MIXED, T, NW>(acc, Pb(Gd + (size_t)gl * bb), P(Pt + (size_t)i * bpbp), 1.0);
+    store<T, NW>(acc, CR + (size_t)i * bpbp, BP, BP, BP);
+  }
+  if (threadIdx.x == 0) a.info_part[(size_t)e * (a.m + 1) + k] = bad_layer >= 0 ? bad_layer + 1 : 0;
+}
+
+// Whether interior k of this solve takes the Hermitian path: H was found exactly
+// Hermitian on the device, eta_d = 0, and the interior holds no lead (k > 0).
+__device__ __forceinline__ bool herm_interior(const DDArgs& a, int k) {
+  return a.herm != nullptr && *a.herm != 0 && a.eta_d == 0.0 && k > 0;
+}
+
+template <int T, int NW, int MIXED>
+__global__ __launch_bounds__(64 * NW, 1) void ddrgf_interior_kernel(DDArgs a) {
+  __shared__ GJShared sh;
+  const int c = blockIdx.x;
+  if (!MIXED && herm_interior(a, c % a.m))
+    interior_herm<T, NW, MIXED>(a, c, sh);
+  else
+    interior_general<T, NW, MIXED>(a, c, sh);
+}
+
 // ---------------------------------------------------------------------------
 // 2. reduced system on the separators
 // ---------------------------------------------------------------------------
@@ -258,6 +389,8 @@ __global__ __launch_bounds__(64 * NW, 1) void ddrgf_recover_kernel(DDArgs a) {
   const double2* CR = ws + (size_t)6 * nmax * bpbp;
   const double2* RL = ws + (size_t)7 * nmax * bpbp;
   const double2* RR = ws + (size_t)8 * nmax * bpbp;
+  // Hermitian interiors keep RL = CL^H and RR = CR^H implicit
+  const bool herm = herm_interior(a, k);
   double2* VL = ws + (size_t)9 * nmax * bpbp;     // 1 block
   double2* VR = VL + bpbp;                         // 1 block (reuses the spare blocks)
   const double2* GS = a.GS + (size_t)e * 3 * m * bb;
@@ -271,6 +404,9 @@ __global__ __launch_bounds__(64 * NW, 1) void ddrgf_recover_kernel(DDArgs a) {
   double2* Gd = Gout + (size_t)a.l * bb;
   double2* Gu = Gout + (size_t)2 * a.l * bb;
   auto blk = [&](const double2* base, int i) { return opnd(base + (size_t)i * bpbp, BP, BP, BP); };
+  auto rblk = [&](const double2* base, const double2* cbase, int i) {
+    return herm ? opnd(cbase + (size_t)i * bpbp, BP, BP, BP, 1) : blk(base, i);
+  };
 
   Acc<T, NW> acc;
   // two-term products [X, Y] [Z1; Z2] as one product over a doubled k range when mixed
@@ -310,7 +446,7 @@ __global__ __launch_bounds__(64 * NW, 1) void ddrgf_recover_kernel(DDArgs a) {
       const int j = i + d;
       if (j < 0 || j >= n) continue;
       double2* dst = (d == 0 ? Gd : (d < 0 ? Gl : Gu)) + (size_t)gi * bb;
-      gemm2(opnd(VR, BP, BP, BP), blk(RR, j), opnd(VL, BP, BP, BP), blk(RL, j), left);
+      gemm2(opnd(VR, BP, BP, BP), rblk(RR, CR, j), opnd(VL, BP, BP, BP), rblk(RL, CL, j), left);
       add_from<T, NW>(acc, opnd(dst, b, b, b));
       store<T, NW>(acc, dst, b, b, b);
     }
@@ -318,13 +454,13 @@ __global__ __launch_bounds__(64 * NW, 1) void ddrgf_recover_kernel(DDArgs a) {
   }
   // G_{qR,e} = -(G_S(k,k-1) RL_{n-1} + G_S(k,k) RR_{n-1});  G_{qL,a} = -(G_S(k-1,k-1) RL_0 + G_S(k-1,k) RR_0)
   acc_zero<T, NW>(acc);
-  if (left) mma<T, NW>(acc, ZRL, blk(RL, n - 1), -1.0);
-  mma<T, NW>(acc, ZRR, blk(RR, n - 1), -1.0);
+  if (left) mma<T, NW>(acc, ZRL, rblk(RL, CL, n - 1), -1.0);
+  mma<T, NW>(acc, ZRR, rblk(RR, CR, n - 1), -1.0);
   store<T, NW>(acc, Gl + (size_t)qR * bb, b, b, b);
   if (left) {
     acc_zero<T, NW>(acc);
-    mma<T, NW>(acc, ZLL, blk(RL, 0), -1.0);
-    mma<T, NW>(acc, ZLR, blk(RR, 0), -1.0);
+    mma<T, NW>(acc, ZLL, rblk(RL, CL, 0), -1.0);
+    mma<T, NW>(acc, ZLR, rblk(RR, CR, 0), -1.0);
     store<T, NW>(acc, Gu + (size_t)qL * bb, b, b, b);
   }
   // separator diagonal block
@@ -446,6 +582,14 @@ extern template hipError_t launch_dd_T<7>(const DDArgs& a, hipStream_t s);
 extern template hipError_t launch_dd_T<8>(const DDArgs& a, hipStream_t s);
 
 hipError_t launch_ddrgf(const DDArgs& a, hipStream_t s) {
+  if (a.herm) {
+    hipLaunchKernelGGL(herm_flag_init_kernel, dim3(1), dim3(64), 0, s, a.herm);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(herm_check_kernel, dim3(1024), dim3(256), 0, s, a.H, a.l, a.b, a.herm);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    ktime_mark("herm_check_kernel", s);
+  }
   switch (padded_block(a.b) / 16) {
     case 1: return launch_dd_T<1>(a, s);
     case 2: return launch_dd_T<2>(a, s);

@@ -96,6 +96,7 @@ struct DDArgs {
   double2* ws_fin;           // [ne][4][bp][bp]
   int mixed;                 // 1: products on FP32 MFMA, FP64 pivots + one refinement step
   double kappa_max;          // as SweepArgs::kappa_max (reduced system)
+  int* herm;                 // device flag: H exactly Hermitian (set by the check kernel)
 };
 
 size_t ddrgf_interior_ws_elems(int nmax, int bp);
@@ -118,7 +119,7 @@ struct BatchArgs {
   double kappa_max;                 // as SweepArgs::kappa_max
 };
 
-hipError_t launch_rgf_batched(const BatchArgs& a, int grid, hipStream_t s);
+hipError_t launch_rgf_batched(const BatchArgs& a, int grid, int waves, hipStream_t s);
 
 // Native n-diagonal sweep (w >= 1), one workgroup per energy.
 struct NSweepArgs {

@@ -334,12 +334,13 @@ hipError_t launch_rgf_sweep(const SweepArgs& a, hipStream_t s) {
 // the next queue entry with one atomic increment of a counter in the workspace, runs
 // the whole chain with the code path of its block size, and stops when the queue is
 // empty (every workgroup reaches that test, so the grid always drains).  Each
-// workgroup owns one workspace slot sized for the largest chain.
+// workgroup owns one workspace slot sized for the largest chain.  NW (4 or 8 waves
+// per workgroup, two or one workgroups per compute unit) is the plan's tile choice.
 // ---------------------------------------------------------------------------
-template <int MIXED>
-__global__ __launch_bounds__(512, 1) void rgf_batched_kernel(BatchArgs a) {
+template <int MIXED, int NW>
+__global__ __launch_bounds__(64 * NW, 8 / NW) void rgf_batched_kernel(BatchArgs a) {
   __shared__ GJShared sh;
-  __shared__ double red[8];
+  __shared__ double red[NW];
   __shared__ int s_item;
   double2* ws = a.ws_slots + (size_t)blockIdx.x * a.ws_slot;
   for (;;) {
@@ -351,13 +352,9 @@ __global__ __launch_bounds__(512, 1) void rgf_batched_kernel(BatchArgs a) {
     const int inst = a.queue[item];
     const int d = a.inst_dev[inst], e = a.inst_energy[inst];
     const rgf_batch_device_t dv = a.devs[d];
-    // the shapes come from the plan (the workspace slots are sized for them); a device
-    // table whose shape differs is reported and the instance skipped
+    // the shapes come from the plan, for which the workspace slots are sized; the
+    // table's shape fields are not read
     const int l = a.dev_shape[2 * d], b = a.dev_shape[2 * d + 1];
-    if (dv.num_layers != l || dv.block_size != b) {
-      if (threadIdx.x == 0) dv.info[e] = RGF_INFO_TABLE_MISMATCH;
-      continue;
-    }
     const size_t bb = (size_t)b * b;
     const double2* H = static_cast<const double2*>(dv.H);
     Chain ch;
@@ -382,10 +379,14 @@ __global__ __launch_bounds__(512, 1) void rgf_batched_kernel(BatchArgs a) {
     ch.dlen = 1;
     ch.kappa_max = a.kappa_max;
     switch (b >> 4) {
-      case 2: run_chain<2, 8, MIXED>(ch, sh, red); break;
-      case 4: run_chain<4, 8, MIXED>(ch, sh, red); break;
-      case 6: run_chain<6, 8, MIXED>(ch, sh, red); break;
-      case 8: run_chain<8, 8, MIXED>(ch, sh, red); break;
+      case 1: run_chain<1, NW, MIXED>(ch, sh, red); break;
+      case 2: run_chain<2, NW, MIXED>(ch, sh, red); break;
+      case 3: run_chain<3, NW, MIXED>(ch, sh, red); break;
+      case 4: run_chain<4, NW, MIXED>(ch, sh, red); break;
+      case 5: run_chain<5, NW, MIXED>(ch, sh, red); break;
+      case 6: run_chain<6, NW, MIXED>(ch, sh, red); break;
+      case 7: run_chain<7, NW, MIXED>(ch, sh, red); break;
+      case 8: run_chain<8, NW, MIXED>(ch, sh, red); break;
       default: break;   // rejected at plan creation
     }
   }
@@ -395,14 +396,21 @@ __global__ void reset_counter_kernel(int* counter) {
   if (threadIdx.x == 0 && blockIdx.x == 0) counter[0] = 0;
 }
 
-hipError_t launch_rgf_batched(const BatchArgs& a, int grid, hipStream_t s) {
+hipError_t launch_rgf_batched(const BatchArgs& a, int grid, int waves, hipStream_t s) {
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, s, a.counter);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
-  if (a.mixed)
-    hipLaunchKernelGGL((rgf_batched_kernel<1>), dim3(grid), dim3(512), 0, s, a);
-  else
-    hipLaunchKernelGGL((rgf_batched_kernel<0>), dim3(grid), dim3(512), 0, s, a);
+  if (waves == 4) {
+    if (a.mixed)
+      hipLaunchKernelGGL((rgf_batched_kernel<1, 4>), dim3(grid), dim3(256), 0, s, a);
+    else
+      hipLaunchKernelGGL((rgf_batched_kernel<0, 4>), dim3(grid), dim3(256), 0, s, a);
+  } else {
+    if (a.mixed)
+      hipLaunchKernelGGL((rgf_batched_kernel<1, 8>), dim3(grid), dim3(512), 0, s, a);
+    else
+      hipLaunchKernelGGL((rgf_batched_kernel<0, 8>), dim3(grid), dim3(512), 0, s, a);
+  }
   return hipGetLastError();
 }
 #endif  // RGFK_BATCHED_TU

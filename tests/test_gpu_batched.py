@@ -53,6 +53,23 @@ def test_small_uneven_batch(lib, schedule):
     check_instances(f"batched/{schedule}", items)
 
 
+@pytest.mark.parametrize("waves", [8, 4])
+def test_block_sizes_and_tiles(lib, waves):
+    """Every block size that is a multiple of 16 (not only those of the 64-device
+    workload), with one and with two workgroups per compute unit."""
+    import torch
+    shapes = [(6, 16, 2), (5, 48, 2), (4, 80, 1), (3, 112, 2), (7, 32, 1), (2, 128, 1), (5, 64, 1), (3, 96, 1)]
+    wls = [make_random(l, b, 1, ne, seed=3500 + l + b, eta=1e-3) for (l, b, ne) in shapes]
+    outs = lib.solve_batched(to_dev(wls), 0.0, waves=waves)
+    torch.cuda.synchronize()
+    items = []
+    for wl, (G, T, info) in zip(wls, outs):
+        G, T, info = G.cpu().numpy(), T.cpu().numpy(), info.cpu().numpy()
+        assert np.all(info == 0)
+        items += [(wl, wl, e, G[e], T[e]) for e in range(wl.ne)]
+    check_instances(f"batched/waves{waves}", items)
+
+
 def test_graph_replays_match_eager(lib):
     """Captured on a side stream; three replays, eager torch work and host syncs in
     between, each bitwise equal to a direct launch on the default stream."""

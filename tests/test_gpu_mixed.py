@@ -46,18 +46,18 @@ def check_mixed(label, G, T, info, energies, refs, b, emul=None):
     return n_mixed
 
 
-@pytest.mark.parametrize("l,b,eta_d", [(16, 16, 0.0), (20, 48, 0.5), (12, 128, 1.0), (33, 37, 0.5),
-                                       (24, 32, 0.0)])
+@pytest.mark.parametrize("l,b,eta_d", [(16, 16, 0.0), (20, 48, 4.0), (12, 128, 4.0), (33, 37, 4.0),
+                                       (24, 32, 0.0), (20, 48, 0.5)])
 def test_mixed_rgf_small(lib, l, b, eta_d):
-    """Small systems, some with device broadening eta_d (well-conditioned pivots, so
-    FP32 products are kept) and some without."""
+    """Small systems, some with a large device broadening eta_d = 4 (pivots with
+    kappa_1 well below 1e-5 * 2^24, so FP32 products must be kept) and some without."""
     wl = make_config(1, ne=3) if (l, b) == (16, 16) else make_random(l, b, 1, 3, seed=2100 + l + b, eta=1e-3)
     G, T, info = run_gpu_dev(lib, wl, precision="fp32", eta_d=eta_d)
     es = range(wl.ne)
     refs = oracle_results("rgf", wl, es, eta_d=eta_d)
     emul = oracle_results("mixed", wl, es, eta_d=eta_d)
     n = check_mixed(f"mixed l={l} b={b} eta_d={eta_d}", G, T.cpu().numpy(), info.cpu().numpy(), es, refs, b, emul)
-    if eta_d >= 0.5:
+    if eta_d >= 4.0:
         assert n == wl.ne   # these are well conditioned: mixed products must be used
 
 

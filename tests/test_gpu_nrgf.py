@@ -2,8 +2,9 @@
 under the fixed rule of tests/parity.py:
 
 * sequential: the native n-diagonal sweep (Sec. 2.3) against the oracle's n-RGF;
-* DDRGF with separators of w layers against the oracle's DDRGF (same algorithm),
-  its distance to the exact band printed beside.
+* DDRGF with separators of w layers against the oracle's DDRGF (same algorithm)
+  under the DDRGF rule of tests/parity.py, its distance to the exact band printed
+  beside.
 At the full pentadiagonal size (512 layers of 64, 128 energies) 17 energies spread
 over the grid are compared for each method, and two of them also against the
 extended-precision reference.
@@ -11,9 +12,9 @@ extended-precision reference.
 import numpy as np
 import pytest
 
-from parity import check_fp64, fp64_bound, gpu_energy, oracle_results, rel, terr
+from parity import check_dd, check_fp64, fp64_bound, gpu_energy, oracle_results, rel, terr
 from test_gpu_rgf import free_gpu, run_gpu, run_gpu_dev
-from workloads import make_config, make_random
+from workloads import make_config, make_dominant, make_random
 
 pytestmark = pytest.mark.gpu
 
@@ -36,9 +37,7 @@ def test_ddrgf_ndiagonal(lib, l, b, w, m):
     G, T, info = run_gpu(lib, wl, method="ddrgf", domains=m)
     assert np.all(info == 0)
     refs = oracle_results("ddrgf", wl, range(2), m=m)
-    check_fp64(f"ddrgf l={l} b={b} w={w} m={m}", G, T, range(2), refs, w, w * b)
-    for e, x in zip(range(2), oracle_results("dense", wl, range(2))):
-        print(f"  energy {e}: DDRGF vs exact band: GPU {rel(gpu_energy(G, e, w), x['G']):.2e}", flush=True)
+    check_dd(f"ddrgf l={l} b={b} w={w} m={m}", G, T, range(2), refs, oracle_results("dense", wl, range(2)), w)
 
 
 def test_config3_sequential(lib):
@@ -61,7 +60,25 @@ def test_config3_ddrgf(lib):
     G, T, info = run_gpu_dev(lib, wl, method="ddrgf", domains=16)
     assert bool((info == 0).all())
     refs = oracle_results("ddrgf", ("config", 3), C3_SAMPLE, m=16)
-    check_fp64("config3 ddrgf", G, T.cpu().numpy(), C3_SAMPLE, refs, 2, 2 * wl.b)
+    exact = oracle_results("nrgf", ("config", 3), C3_SAMPLE)
+    check_dd("config3 ddrgf", G, T.cpu().numpy(), C3_SAMPLE, refs, exact, 2)
+    del G
+    free_gpu()
+
+
+def test_dominant_pentadiagonal_ddrgf(lib):
+    """512 x 64 block pentadiagonal, block diagonally dominant (the paper's class of
+    test matrices), 16 domains: 9 energies spread over the grid within the DDRGF
+    rule, here down to the FP64 target, against the oracle's DDRGF and n-RGF."""
+    src = ("dominant", 512, 64, 2, 128, 203)
+    wl = make_dominant(*src[1:])
+    es = list(range(0, 128, 16)) + [127]
+    G, T, info = run_gpu_dev(lib, wl, method="ddrgf", domains=16)
+    assert bool((info == 0).all())
+    refs = oracle_results("ddrgf", src, es, m=16)
+    exact = oracle_results("nrgf", src, es)
+    rows = check_dd("dominant 512x64 w=2 ddrgf", G, T.cpu().numpy(), es, refs, exact, 2)
+    assert max(r[3] for r in rows) <= 1e-9, "the rule should be tight on a well-conditioned system"
     del G
     free_gpu()
 

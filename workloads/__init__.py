@@ -11,6 +11,7 @@ from .generators import (  # noqa: F401
     band_block,
     lead_sigma,
     make_config,
+    make_dominant,
     make_uniform_chain,
     midpoint_grid,
     random_hermitian_band,

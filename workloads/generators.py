@@ -179,6 +179,35 @@ def make_uniform_chain(l: int, b: int, ne: int, seed: int = 106, eta: float = 1e
     return wl
 
 
+def make_dominant(l: int, b: int, w: int, ne: int, seed, e_lo=-2.0, e_hi=2.0, eta=1e-6,
+                  name="dominant") -> Workload:
+    """Block diagonally dominant random system, the class of test matrices of the
+    paper's numerical experiments (Sec. "Numerical experiments", RGF n = 3): the
+    random Hermitian band of :func:`random_hermitian_band` with every diagonal block
+    shifted by s I, s = ||H_ii||_2 max + 2 (sum over j != i of ||H_ij||_2) max +
+    max(|e_lo|, |e_hi|) + 1 (the lead self-energy has |sigma| <= 1).  Then
+    ||(E - H_ii - s - Sigma)^{-1}|| * sum_j ||H_ij|| <= 1/2 at every energy of the
+    grid, so every Schur pivot and every closed DDRGF interior is well
+    conditioned.  The device levels sit far above the lead band, so T is
+    tiny; the point is the selected inverse."""
+    H = random_hermitian_band(l, b, w, seed)
+    off = np.zeros(l)
+    for k in range(-w, w + 1):
+        if k == 0:
+            continue
+        for i in range(l):
+            if 0 <= i + k < l:
+                off[i] += np.linalg.norm(H[w + k, i], 2)
+    diag = max(np.linalg.norm(H[w, i], 2) for i in range(l))
+    s = diag + 2.0 * off.max() + max(abs(e_lo), abs(e_hi)) + 1.0
+    H[w] += s * np.eye(b)[None]
+    E = midpoint_grid(e_lo, e_hi, ne)
+    sig = lead_sigma(E, eta, b)
+    wl = Workload(name, l, b, w, H, E, sig, sig.copy(), eta)
+    wl.meta.update(shift=s)
+    return wl
+
+
 # The five benchmark workloads (sizes, grids and broadenings) plus the uniform chain.
 CONFIGS = {
     1: dict(l=16, b=16, w=1, ne=4, e_lo=-1.0, e_hi=1.0, eta=1e-3, seed=101, domains=2),
