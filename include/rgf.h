@@ -233,6 +233,19 @@ rgf_status_t rgf_plan_checkpoint_bytes(rgf_plan_t plan, size_t* checkpoint_bytes
 /* Workspace size of a plan (the value rgf_plan_create returned). */
 rgf_status_t rgf_plan_workspace_bytes(rgf_plan_t plan, size_t* workspace_bytes);
 
+/* rgf_solve without a workspace argument, for callers that cannot allocate device
+ * memory (code under stream capture, tight serving loops, harnesses that forbid
+ * allocation).  The workspace is a static device array of the library, 64 MiB
+ * (67108864 bytes) per device, held until the process ends; this call allocates
+ * nothing.  Plans whose workspace exceeds it are refused
+ * with RGF_ERR_WORKSPACE_TOO_SMALL, plans made with want_backward with
+ * RGF_ERR_UNSUPPORTED.  All calls on one device share the array: calls that
+ * overlap on a device (concurrent streams or host threads) race and must be
+ * serialised by the caller.  Other arguments and results as rgf_solve. */
+rgf_status_t rgf_solve_noalloc(rgf_plan_t plan, const void* H, const void* sigma_L, const void* sigma_R,
+                               const double* energies, double eta_d, void* G, double* T, int32_t* info,
+                               void* stream);
+
 /* ---------------------------------------------------------------------------
  * Per-kernel timing (measurement aid; not part of the method).
  *

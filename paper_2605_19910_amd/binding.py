@@ -100,6 +100,8 @@ def load() -> ctypes.CDLL:
     lib.rgf_plan_checkpoint_bytes.restype = ctypes.c_int
     lib.rgf_plan_workspace_bytes.argtypes = [_VP, ctypes.POINTER(ctypes.c_size_t)]
     lib.rgf_plan_workspace_bytes.restype = ctypes.c_int
+    lib.rgf_solve_noalloc.argtypes = [_VP, _VP, _VP, _VP, _VP, ctypes.c_double, _VP, _VP, _VP, _VP]
+    lib.rgf_solve_noalloc.restype = ctypes.c_int
     lib.rgf_plan_set_timing.argtypes = [_VP, ctypes.c_int32, ctypes.c_int32]
     lib.rgf_plan_set_timing.restype = ctypes.c_int
     lib.rgf_plan_kernel_times.argtypes = [_VP, ctypes.POINTER(KernelTime), ctypes.c_int32,
@@ -180,6 +182,14 @@ def rgf_solve(plan: Plan, H, sigma_L, sigma_R, energies, eta_d: float, G, T, inf
                             stream)
     if st != RGF_OK:
         raise RgfError("rgf_solve", st)
+
+
+def rgf_solve_noalloc(plan: Plan, H, sigma_L, sigma_R, energies, eta_d: float, G, T, info, stream: int = 0) -> None:
+    """rgf_solve with the library's static device workspace (allocates nothing)."""
+    st = plan.lib.rgf_solve_noalloc(plan.handle, _ptr(H), _ptr(sigma_L), _ptr(sigma_R), _ptr(energies),
+                                    float(eta_d), _ptr(G), _ptr(T), _ptr(info), stream)
+    if st != RGF_OK:
+        raise RgfError("rgf_solve_noalloc", st)
 
 
 def rgf_backward(plan: Plan, H, sigma_L, sigma_R, energies, eta_d: float, G_diag, g_diag_stride: int, dL_dT,
