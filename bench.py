@@ -355,8 +355,11 @@ def main():
         times = plan.kernel_times()
         plan.set_timing(False)
         res["kernel_ms_avg"] = {k: v[0] / v[1] for k, v in times.items()}
+        if method == "rgf":
+            res["workgroups_per_energy"] = plan.split_workgroups()
         herm = is_hermitian_band(wl.H) and wl.eta_d == 0.0
-        flops_of = {"rgf_sweep_kernel": rgf_flops_per_energy(l, b) * ne if method == "rgf" else None,
+        rgf_fl = rgf_flops_per_energy(l, b) * ne if method == "rgf" else None
+        flops_of = {"rgf_sweep_kernel": rgf_fl, "rgf_split_kernel": rgf_fl,
                     "ddrgf_interior_kernel": ddrgf_interior_flops(l, b, args.domains, ne, herm),
                     "ddrgf_recover_kernel": ddrgf_recover_flops(l, b, args.domains, ne)}
         dom = max(times, key=lambda k: times[k][0])

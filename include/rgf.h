@@ -81,6 +81,13 @@ typedef enum {
 #define RGF_INFO_FP64_PRODUCTS 0x40000000
 #define RGF_INFO_STATUS_MASK 0x3fffffff
 
+/* Status bit in info[e] of a sequential solve run with several workgroups per
+ * energy (rgf_plan_set_split): a workgroup of that energy gave up waiting for the
+ * others at a group barrier.  That energy's outputs are undefined (T is NaN).  Not
+ * expected in practice (the launch is cooperative, so every workgroup is resident);
+ * it bounds the wait if one is ever missing. */
+#define RGF_INFO_SYNC_TIMEOUT 0x20000000
+
 /* want_backward flags */
 #define RGF_BACKWARD_ONSITE 1   /* on-site energy gradient */
 #define RGF_BACKWARD_BAND 2     /* gradient with respect to the whole band of H (sizes the workspace) */
@@ -121,6 +128,23 @@ rgf_status_t rgf_plan_destroy(rgf_plan_t plan);
 rgf_status_t rgf_solve(rgf_plan_t plan, const void* H, const void* sigma_L, const void* sigma_R,
                        const double* energies, double eta_d, void* G, double* T, int32_t* info,
                        void* workspace, size_t workspace_bytes, void* stream);
+
+/* Several workgroups per energy for rgf_solve.  With fewer energies than compute
+ * units, the sequential sweep of Algorithm 1 (w = 1, FP64, plans without
+ * want_backward, padded block size 64 or 128) can give each energy K = 2 or 4
+ * workgroups: each computes a row slab of every block product, the first also
+ * inverts the Schur pivots, and they meet at bounded group barriers (cooperative
+ * launch, so all are resident).  Results are bitwise those of one workgroup per
+ * energy.  workgroups_per_energy: 0 = the largest K in {4, 2} whose grid fits the
+ * device's co-resident capacity (1 when none does), 1 = never split, 2 or 4 = that K
+ * when it fits (else 1).  spin_limit: polls of a group barrier before a workgroup
+ * gives up (RGF_INFO_SYNC_TIMEOUT); 0 = the default (2^22).  The choice is made at
+ * the next solve, on its device; streams under capture always use one workgroup
+ * per energy.  Returns RGF_ERR_INVALID_ARG for other values. */
+rgf_status_t rgf_plan_set_split(rgf_plan_t plan, int32_t workgroups_per_energy, int64_t spin_limit);
+
+/* Workgroups per energy used by the plan's last rgf_solve (1 before any). */
+rgf_status_t rgf_plan_split_workgroups(rgf_plan_t plan, int32_t* workgroups_per_energy);
 
 /* DDRGF (Algorithm 2, one level): interiors of every energy are eliminated
  * independently, separators are stitched through the reduced block-tridiagonal

@@ -18,6 +18,7 @@ BACKWARD_ONSITE = 1                 # want_backward flags (RGF_BACKWARD_ONSITE /
 BACKWARD_BAND = 2
 INFO_FP64_PRODUCTS = 0x40000000     # RGF_INFO_FP64_PRODUCTS: a mixed solve recomputed the energy in FP64
 INFO_STATUS_MASK = 0x3fffffff
+INFO_SYNC_TIMEOUT = 0x20000000
 STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported configuration", 3: "out of host memory",
           4: "workspace missing or too small", 5: "HIP runtime error",
           6: "plan does not match the entry point"}
@@ -102,6 +103,10 @@ def load() -> ctypes.CDLL:
     lib.rgf_plan_workspace_bytes.restype = ctypes.c_int
     lib.rgf_solve_noalloc.argtypes = [_VP, _VP, _VP, _VP, _VP, ctypes.c_double, _VP, _VP, _VP, _VP]
     lib.rgf_solve_noalloc.restype = ctypes.c_int
+    lib.rgf_plan_set_split.argtypes = [_VP, ctypes.c_int32, ctypes.c_int64]
+    lib.rgf_plan_set_split.restype = ctypes.c_int
+    lib.rgf_plan_split_workgroups.argtypes = [_VP, ctypes.POINTER(ctypes.c_int32)]
+    lib.rgf_plan_split_workgroups.restype = ctypes.c_int
     lib.rgf_plan_set_timing.argtypes = [_VP, ctypes.c_int32, ctypes.c_int32]
     lib.rgf_plan_set_timing.restype = ctypes.c_int
     lib.rgf_plan_kernel_times.argtypes = [_VP, ctypes.POINTER(KernelTime), ctypes.c_int32,
@@ -139,6 +144,20 @@ class Plan:
         self.checkpoint_bytes = int(ck.value)
         self.method = method
         self.l, self.b, self.w, self.ne = l, b, w, ne
+
+    def set_split(self, workgroups_per_energy: int = 0, spin_limit: int = 0) -> None:
+        """Workgroups per energy of the sequential sweep (0 = automatic, 1 = off, 2, 4)."""
+        st = self.lib.rgf_plan_set_split(self.handle, int(workgroups_per_energy), int(spin_limit))
+        if st != RGF_OK:
+            raise RgfError("rgf_plan_set_split", st)
+
+    def split_workgroups(self) -> int:
+        """Workgroups per energy used by the last rgf_solve."""
+        k = ctypes.c_int32(0)
+        st = self.lib.rgf_plan_split_workgroups(self.handle, ctypes.byref(k))
+        if st != RGF_OK:
+            raise RgfError("rgf_plan_split_workgroups", st)
+        return int(k.value)
 
     def set_timing(self, enable: bool = True, max_marks: int = 256) -> None:
         """Record a HIP event after every kernel this plan's solves launch."""

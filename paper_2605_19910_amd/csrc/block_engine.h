@@ -502,11 +502,8 @@ __device__ __forceinline__ uint64_t pivot_key(double k, int row) {
   return (hi << 7) | (uint64_t)(127 - row);
 }
 
-__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int off) {
-  const int lo = __shfl_xor((int)(uint32_t)v, off, 64);
-  const int hi = __shfl_xor((int)(uint32_t)(v >> 32), off, 64);
-  return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
-}
+// Wave-wide maximum of a 64-bit key (device library routine).
+extern "C" __device__ __attribute__((const)) unsigned long long __ockl_wfred_max_u64(unsigned long long);
 
 // LDS scratch of the Gauss-Jordan inversion.
 struct GJShared {
@@ -579,11 +576,7 @@ __device__ __forceinline__ void gj_invert(Acc<T, NW>& acc, double2* g, GJShared&
           u = kq > u ? kq : u;
         }
       }
-#pragma unroll
-      for (int off = 32; off >= 1; off >>= 1) {
-        const uint64_t o = shfl_xor_u64(u, off);
-        u = o > u ? o : u;
-      }
+      u = __ockl_wfred_max_u64(u);   // wave maximum through DPP row operations
       const bool col_bad = (u >> 7) <= 2 || __ballot(nf) != 0;   // zero or non-finite candidates
       const int pr = 127 - (int)(u & 127);
       if ((pr & 63) == l) pivmask |= 1u << (pr >> 6);

@@ -20,6 +20,11 @@ struct rgf_plan_s {
   // rest is scratch shared by the forward sweep and the adjoint
   int nd = 0, dlen = 0, nch = 0;
   size_t ck_chain = 0, ck_bytes = 0, off_fwd = 0, off_adj = 0, adj_wg = 0, off_grad = 0, off_hpart = 0;
+  // split sweep (several workgroups per energy): group counters at off_sync (plain
+  // sequential w = 1 plans); the requested and the resolved workgroups per energy
+  size_t off_sync = 0;
+  int split_want = 0, split_k = -1, split_dev = -1, split_used = 1;
+  long long split_spin = 0;
   // DDRGF workspace layout (byte offsets)
   size_t dd_int_chain, dd_red_chain;
   size_t off_int, off_ms, off_gs, off_gsrow, off_red, off_fin, off_info, off_herm;
@@ -86,6 +91,7 @@ namespace {
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 constexpr double DEFAULT_MIXED_TOLERANCE = 1e-5;
 constexpr int ADJOINT_ENERGY_CHUNKS = 64;
+constexpr long long DEFAULT_SPLIT_SPIN = 1LL << 22;
 // largest pivot kappa_1 with FP32 products: tolerance / 2^-24
 double kappa_limit(double tol) { return (tol > 0.0 ? tol : DEFAULT_MIXED_TOLERANCE) * 16777216.0; }
 }
@@ -129,6 +135,24 @@ rgf_status_t validate(const rgf_desc_t* d) {
   return RGF_OK;
 }
 
+// Workgroups per energy for a plain sequential solve on this stream's device.
+int split_for(rgf_plan_s* p, hipStream_t st) {
+  const rgf_desc_t& d = p->d;
+  if (d.half_bandwidth != 1 || d.method != RGF_METHOD_SEQUENTIAL || d.precision != RGF_FP64 ||
+      d.want_backward || p->split_want == 1)
+    return 1;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return 1;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return 1;
+  std::lock_guard<std::mutex> lock(p->mu);
+  if (p->split_k < 0 || p->split_dev != dev) {
+    p->split_k = rgfk::split_workgroups((int)d.block_size, (int)d.num_energies, p->split_want);
+    p->split_dev = dev;
+  }
+  return p->split_k;
+}
+
 }  // namespace
 
 extern "C" {
@@ -148,6 +172,11 @@ rgf_status_t rgf_plan_create(const rgf_desc_t* desc, rgf_plan_t* plan, size_t* w
   else
     p->ws_chain = rgfk::nrgf_ws_chain_elems((int)desc->num_layers, w, p->bp);
   p->ws_bytes = p->ws_chain * sizeof(double2) * (size_t)desc->num_energies;
+  if (w == 1 && desc->method == RGF_METHOD_SEQUENTIAL && !desc->want_backward) {
+    // group counters of the split sweep, 64 bytes per energy
+    p->off_sync = align256(p->ws_bytes);
+    p->ws_bytes = p->off_sync + (size_t)64 * desc->num_energies;
+  }
   if (desc->want_backward) {
     const int l = (int)desc->num_layers, ne = (int)desc->num_energies, b = (int)desc->block_size;
     const size_t bpbp = (size_t)p->bp * p->bp;
@@ -409,7 +438,22 @@ rgf_status_t rgf_solve(rgf_plan_t plan, const void* H, const void* sigma_L, cons
   a.kappa_max = kappa_limit(d.mixed_tolerance);
   a.nd = d.want_backward ? plan->nd : 0;
   a.dlen = d.want_backward ? plan->dlen : 0;
-  hipError_t e = rgfk::launch_rgf_sweep(a, static_cast<hipStream_t>(stream));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int K = split_for(plan, st);
+  if (K > 1) {
+    a.sync = reinterpret_cast<unsigned*>(static_cast<char*>(workspace) + plan->off_sync);
+    a.spin_limit = plan->split_spin > 0 ? plan->split_spin : DEFAULT_SPLIT_SPIN;
+    hipError_t e = rgfk::launch_rgf_split(a, K, st);
+    if (e == hipSuccess) {
+      plan->split_used = K;
+      return RGF_OK;
+    }
+    // not launchable right now (e.g. the cooperative grid does not fit): one
+    // workgroup per energy instead
+    (void)hipGetLastError();
+  }
+  plan->split_used = 1;
+  hipError_t e = rgfk::launch_rgf_sweep(a, st);
   return e == hipSuccess ? RGF_OK : RGF_ERR_HIP;
 }
 
@@ -517,6 +561,24 @@ rgf_status_t rgf_backward(rgf_plan_t plan, const void* H, const void* sigma_L, c
 rgf_status_t rgf_plan_workspace_bytes(rgf_plan_t plan, size_t* workspace_bytes) {
   if (!plan || !workspace_bytes) return RGF_ERR_INVALID_ARG;
   *workspace_bytes = plan->ws_bytes;
+  return RGF_OK;
+}
+
+rgf_status_t rgf_plan_set_split(rgf_plan_t plan, int32_t workgroups_per_energy, int64_t spin_limit) {
+  if (!plan || spin_limit < 0) return RGF_ERR_INVALID_ARG;
+  if (workgroups_per_energy != 0 && workgroups_per_energy != 1 && workgroups_per_energy != 2 &&
+      workgroups_per_energy != 4)
+    return RGF_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lock(plan->mu);
+  plan->split_want = workgroups_per_energy;
+  plan->split_spin = spin_limit;
+  plan->split_k = -1;
+  return RGF_OK;
+}
+
+rgf_status_t rgf_plan_split_workgroups(rgf_plan_t plan, int32_t* workgroups_per_energy) {
+  if (!plan || !workgroups_per_energy) return RGF_ERR_INVALID_ARG;
+  *workgroups_per_energy = plan->split_used;
   return RGF_OK;
 }
 

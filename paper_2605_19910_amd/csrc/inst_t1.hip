@@ -5,3 +5,4 @@
 #include "ddrgf.hip"
 #include "nrgf_sweep.hip"
 #include "adjoint.hip"
+#include "rgf_split.hip"

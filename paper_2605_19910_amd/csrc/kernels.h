@@ -37,6 +37,8 @@ struct SweepArgs {
   double kappa_max;          // mixed: pivots with a larger kappa_1 send the chain back to FP64
   double2* ck;               // adjoint checkpoints (nd > 0): ck_chain elements per chain, layout
   size_t ck_chain;           // as AdjArgs::ck
+  unsigned* sync;            // split sweep: one group counter per chain, 64 bytes apart
+  long long spin_limit;      // split sweep: polls before a group barrier gives up
 };
 
 // Adjoint of T (one workgroup per (domain, energy chunk)); see adjoint.hip.
@@ -73,6 +75,14 @@ __host__ __device__ inline size_t sweep_ws_chain_elems(int l, int bp) {
 }
 int padded_block(int b);
 hipError_t launch_rgf_sweep(const SweepArgs& a, hipStream_t s);
+
+// Sequential sweep with K workgroups per chain (rgf_split.hip): FP64, plain solve
+// (no checkpoints, no first row), padded block size 64 or 128.  split_workgroups
+// returns the K (4, 2, or 1 = use launch_rgf_sweep) that fits the current device's
+// co-resident capacity for ne chains (want: 0 = largest that fits, else only that
+// K).  launch_rgf_split clears the counters and info, then launches cooperatively.
+int split_workgroups(int b, int ne, int want);
+hipError_t launch_rgf_split(const SweepArgs& a, int K, hipStream_t s);
 
 // DDRGF (Algorithm 2), block tridiagonal, one level.
 struct DDArgs {

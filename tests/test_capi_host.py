@@ -56,7 +56,9 @@ def test_plan_workspace_size(l, b, w, ne):
     binding = _lib()
     p = binding.Plan(l, b, w, ne)
     bp = ((b + 15) // 16) * 16
-    assert p.workspace_bytes == (3 * l + 10) * bp * bp * 16 * ne
+    sweep = (3 * l + 10) * bp * bp * 16 * ne
+    # plus one 64-byte group counter per energy for the split sweep, 256-byte aligned
+    assert p.workspace_bytes == (sweep + 255) // 256 * 256 + 64 * ne
     p.close()
 
 
@@ -126,6 +128,23 @@ def test_backward_plan_workspace_and_mismatch():
     assert lib.rgf_backward(p.handle, f, f, f, f, 0.0, f, 0, f, None, f, f, 16, None) == 4
     with pytest.raises(binding.RgfError):
         binding.Plan(8, 4, 1, 1, want_backward=4)
+
+
+def test_split_arguments():
+    """Workgroups per energy: 0, 1, 2, 4 accepted, anything else and negative spin
+    limits rejected on the host; before any solve the plan reports 1."""
+    binding = _lib()
+    lib = binding.load()
+    p = binding.Plan(8, 64, 1, 2)
+    for k in (0, 1, 2, 4):
+        assert lib.rgf_plan_set_split(p.handle, k, 0) == 0
+    for k in (-1, 3, 5, 8):
+        assert lib.rgf_plan_set_split(p.handle, k, 0) == 1
+    assert lib.rgf_plan_set_split(p.handle, 0, -5) == 1
+    assert lib.rgf_plan_set_split(None, 0, 0) == 1
+    assert p.split_workgroups() == 1
+    assert lib.rgf_plan_split_workgroups(p.handle, None) == 1
+    p.close()
 
 
 def test_timing_argument_errors():
