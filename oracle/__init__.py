@@ -1,4 +1,5 @@
-"""Plain FP64 CPU oracle for RGF / n-diagonal RGF / DDRGF selected inversion.
+"""Plain FP64 CPU oracle for RGF / n-diagonal RGF / DDRGF selected inversion, the
+lesser Green's function on the band and lead self-energies by decimation.
 
 TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
 benchmark's CPU-baseline leg may import this package.  The GPU library never
@@ -30,3 +31,5 @@ from .ext_precision import (  # noqa: F401
     solve_energy_ext,
     transmission_ext,
 )
+from .keldysh import lesser, lesser_dense  # noqa: F401,E402
+from .leads import lead_self_energies, lead_self_energy, surface_gf  # noqa: F401,E402
