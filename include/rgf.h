@@ -129,6 +129,47 @@ rgf_status_t rgf_solve(rgf_plan_t plan, const void* H, const void* sigma_L, cons
                        const double* energies, double eta_d, void* G, double* T, int32_t* info,
                        void* workspace, size_t workspace_bytes, void* stream);
 
+/* Lesser Green's function on the band (the Keldysh equation G^< = G^R Sigma^< G^A,
+ * the stage after the Dyson equation named in the paper's introduction and
+ * outlook).  The lesser self-energies are the leads': Sigma^<_X = i f_X Gamma_X on
+ * the layer lead X attaches to, Gamma_X = i (Sigma_X - Sigma_X^H), f_X =
+ * occupation_X[e] (DEVICE arrays [nE], e.g. Fermi functions of the leads at each
+ * energy); a device broadening eta_d enters G^R only.  Then
+ *   G^<_ij = G_{i,0} Sigma^<_L G_{j,0}^H + G_{i,l-1} Sigma^<_R G_{j,l-1}^H,
+ * with the first and last block columns of G^R from the multipliers of Algorithm
+ * 1's sweep.  Runs rgf_solve (same arguments, results and workspace) and then
+ * writes G_lesser [nE][3][l][b][b] in the layout of G (blocks outside the matrix
+ * are not written; energies whose info is nonzero get NaN).  Sequential plans with
+ * w = 1, FP64, without want_backward (else RGF_ERR_UNSUPPORTED). */
+rgf_status_t rgf_solve_lesser(rgf_plan_t plan, const void* H, const void* sigma_L, const void* sigma_R,
+                              const double* energies, double eta_d, const double* occupation_L,
+                              const double* occupation_R, void* G, void* G_lesser, double* T, int32_t* info,
+                              void* workspace, size_t workspace_bytes, void* stream);
+
+/* Retarded self-energies of a semi-infinite periodic lead at every energy (the
+ * Sigma^r that the selected inversion takes as given input).  The lead repeats
+ * principal layers with on-layer block H00 and coupling H01 to the next layer away
+ * from the device; its surface Green's function g_s = (z - H00 - H01 g_s H01^H)^{-1},
+ * z = E + i eta, is computed by the decimation of Lopez Sancho, Lopez Sancho and
+ * Rubio (J. Phys. F 15, 851 (1985)), each step halving the remaining chain, until
+ * max|alpha_ij| + max|beta_ij| < tolerance (the couplings of the decimated chain),
+ * and sigma[e] = Hc g_s Hc^H with Hc the coupling from the device layer to the lead's
+ * surface layer.  H00, H01, Hc: DEVICE [b][b]; energies: DEVICE [nE]; sigma: DEVICE
+ * out [nE][b][b] (the layout of sigma_L / sigma_R of rgf_solve); steps: DEVICE out
+ * [nE]: the number of decimation steps taken, -1 when max_steps steps did not
+ * converge, -2 when a pivot z - eps was singular or non-finite (sigma NaN in both
+ * cases).  workspace: rgf_lead_workspace_bytes(b, nE) bytes.  Errors: 1 <= b <= 128,
+ * nE >= 1, tolerance > 0, max_steps >= 1, eta >= 0 and non-NULL pointers, else
+ * RGF_ERR_INVALID_ARG (b > 128: RGF_ERR_UNSUPPORTED); a smaller workspace gives
+ * RGF_ERR_WORKSPACE_TOO_SMALL.  Accuracy: where E + i eta is within ~eta of an
+ * eigenvalue of H00 the first steps invert a nearly singular z - eps and the
+ * decimation cancels terms of size 1/eta (FP64 loses ~1e-5 at eta = 1e-6). */
+rgf_status_t rgf_lead_workspace_bytes(int64_t block_size, int64_t num_energies, size_t* workspace_bytes);
+rgf_status_t rgf_lead_self_energy(int64_t block_size, int64_t num_energies, const void* H00, const void* H01,
+                                  const void* Hc, const double* energies, double eta, double tolerance,
+                                  int32_t max_steps, void* sigma, int32_t* steps, void* workspace,
+                                  size_t workspace_bytes, void* stream);
+
 /* Several workgroups per energy for rgf_solve.  With fewer energies than compute
  * units, the sequential sweep of Algorithm 1 (w = 1, FP64, plans without
  * want_backward, padded block size 64 or 128) can give each energy K = 2 or 4

@@ -103,6 +103,14 @@ def load() -> ctypes.CDLL:
     lib.rgf_plan_workspace_bytes.restype = ctypes.c_int
     lib.rgf_solve_noalloc.argtypes = [_VP, _VP, _VP, _VP, _VP, ctypes.c_double, _VP, _VP, _VP, _VP]
     lib.rgf_solve_noalloc.restype = ctypes.c_int
+    lib.rgf_solve_lesser.argtypes = [_VP, _VP, _VP, _VP, _VP, ctypes.c_double, _VP, _VP, _VP, _VP, _VP, _VP, _VP,
+                                     ctypes.c_size_t, _VP]
+    lib.rgf_solve_lesser.restype = ctypes.c_int
+    lib.rgf_lead_workspace_bytes.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)]
+    lib.rgf_lead_workspace_bytes.restype = ctypes.c_int
+    lib.rgf_lead_self_energy.argtypes = [ctypes.c_int64, ctypes.c_int64, _VP, _VP, _VP, _VP, ctypes.c_double,
+                                         ctypes.c_double, ctypes.c_int32, _VP, _VP, _VP, ctypes.c_size_t, _VP]
+    lib.rgf_lead_self_energy.restype = ctypes.c_int
     lib.rgf_plan_set_split.argtypes = [_VP, ctypes.c_int32, ctypes.c_int64]
     lib.rgf_plan_set_split.restype = ctypes.c_int
     lib.rgf_plan_split_workgroups.argtypes = [_VP, ctypes.POINTER(ctypes.c_int32)]
@@ -209,6 +217,68 @@ def rgf_solve_noalloc(plan: Plan, H, sigma_L, sigma_R, energies, eta_d: float, G
                                     float(eta_d), _ptr(G), _ptr(T), _ptr(info), stream)
     if st != RGF_OK:
         raise RgfError("rgf_solve_noalloc", st)
+
+
+def rgf_solve_lesser(plan: Plan, H, sigma_L, sigma_R, energies, eta_d: float, occupation_L, occupation_R, G,
+                     G_lesser, T, info, workspace, stream: int = 0) -> None:
+    st = plan.lib.rgf_solve_lesser(plan.handle, _ptr(H), _ptr(sigma_L), _ptr(sigma_R), _ptr(energies), float(eta_d),
+                                   _ptr(occupation_L), _ptr(occupation_R), _ptr(G), _ptr(G_lesser), _ptr(T),
+                                   _ptr(info), _ptr(workspace), workspace.numel() * workspace.element_size(), stream)
+    if st != RGF_OK:
+        raise RgfError("rgf_solve_lesser", st)
+
+
+def solve_lesser(H, sigma_L, sigma_R, energies, occupation_L, occupation_R, eta_d: float = 0.0,
+                 plan: Optional[Plan] = None) -> Tuple:
+    """Allocate outputs and run rgf_solve_lesser on the current stream.  Returns
+    (G [nE, 3, l, b, b], G_lesser [nE, 3, l, b, b], T [nE], info [nE])."""
+    import torch
+    _, l, b, _ = H.shape
+    ne = energies.shape[0]
+    if plan is None:
+        plan = Plan(l, b, 1, ne)
+    dev = H.device
+    G = torch.empty((ne, 3, l, b, b), dtype=torch.complex128, device=dev)
+    Gl = torch.empty_like(G)
+    T = torch.empty((ne,), dtype=torch.float64, device=dev)
+    info = torch.empty((ne,), dtype=torch.int32, device=dev)
+    ws = torch.empty((plan.workspace_bytes,), dtype=torch.uint8, device=dev)
+    for t, name in ((occupation_L, "occupation_L"), (occupation_R, "occupation_R")):
+        if t.dtype != torch.float64 or not t.is_cuda or t.shape[0] != ne:
+            raise ValueError(f"{name} must be a float64 GPU tensor of one value per energy")
+    rgf_solve_lesser(plan, H, sigma_L, sigma_R, energies, eta_d, occupation_L, occupation_R, G, Gl, T, info, ws,
+                     torch.cuda.current_stream(dev).cuda_stream)
+    return G, Gl, T, info
+
+
+def lead_self_energy(H00, H01, Hc, energies, eta: float, tolerance: float = 1e-14, max_steps: int = 100,
+                     stream: Optional[int] = None) -> Tuple:
+    """Retarded self-energies of a semi-infinite lead at every energy (rgf_lead_self_energy).
+    H00, H01, Hc: complex128 [b, b] GPU tensors; energies: float64 [nE].
+    Returns (sigma [nE, b, b], steps [nE])."""
+    import torch
+    lib = load()
+    b = H00.shape[0]
+    ne = energies.shape[0]
+    for t, name in ((H00, "H00"), (H01, "H01"), (Hc, "Hc")):
+        if t.dtype != torch.complex128 or not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != (b, b):
+            raise ValueError(f"{name} must be a contiguous complex128 [b, b] GPU tensor")
+    if energies.dtype != torch.float64 or not energies.is_cuda:
+        raise ValueError("energies must be a float64 GPU tensor")
+    ws_bytes = ctypes.c_size_t(0)
+    st = lib.rgf_lead_workspace_bytes(b, ne, ctypes.byref(ws_bytes))
+    if st != RGF_OK:
+        raise RgfError("rgf_lead_workspace_bytes", st)
+    dev = H00.device
+    sigma = torch.empty((ne, b, b), dtype=torch.complex128, device=dev)
+    steps = torch.empty((ne,), dtype=torch.int32, device=dev)
+    ws = torch.empty((int(ws_bytes.value),), dtype=torch.uint8, device=dev)
+    s = torch.cuda.current_stream(dev).cuda_stream if stream is None else stream
+    st = lib.rgf_lead_self_energy(b, ne, _ptr(H00), _ptr(H01), _ptr(Hc), _ptr(energies), float(eta), float(tolerance),
+                                  int(max_steps), _ptr(sigma), _ptr(steps), _ptr(ws), int(ws_bytes.value), s)
+    if st != RGF_OK:
+        raise RgfError("rgf_lead_self_energy", st)
+    return sigma, steps
 
 
 def rgf_backward(plan: Plan, H, sigma_L, sigma_R, energies, eta_d: float, G_diag, g_diag_stride: int, dL_dT,

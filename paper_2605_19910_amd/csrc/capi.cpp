@@ -457,6 +457,35 @@ rgf_status_t rgf_solve(rgf_plan_t plan, const void* H, const void* sigma_L, cons
   return e == hipSuccess ? RGF_OK : RGF_ERR_HIP;
 }
 
+rgf_status_t rgf_solve_lesser(rgf_plan_t plan, const void* H, const void* sigma_L, const void* sigma_R,
+                              const double* energies, double eta_d, const double* occupation_L,
+                              const double* occupation_R, void* G, void* G_lesser, double* T, int32_t* info,
+                              void* workspace, size_t workspace_bytes, void* stream) {
+  if (!plan) return RGF_ERR_INVALID_ARG;
+  if (plan->batched || plan->d.method != RGF_METHOD_SEQUENTIAL) return RGF_ERR_PLAN_MISMATCH;
+  const rgf_desc_t& d = plan->d;
+  if (d.half_bandwidth != 1 || d.precision != RGF_FP64 || d.want_backward) return RGF_ERR_UNSUPPORTED;
+  if (!occupation_L || !occupation_R || !G_lesser) return RGF_ERR_INVALID_ARG;
+  rgf_status_t st = rgf_solve(plan, H, sigma_L, sigma_R, energies, eta_d, G, T, info, workspace,
+                              workspace_bytes, stream);
+  if (st != RGF_OK) return st;
+  TimedScope timed(plan, static_cast<hipStream_t>(stream));
+  rgfk::LesserArgs a{};
+  a.sigL = static_cast<const double2*>(sigma_L);
+  a.sigR = static_cast<const double2*>(sigma_R);
+  a.fL = occupation_L;
+  a.fR = occupation_R;
+  a.G = static_cast<const double2*>(G);
+  a.info = info;
+  a.Gless = static_cast<double2*>(G_lesser);
+  a.ws = reinterpret_cast<double2*>(static_cast<char*>(workspace) + plan->off_fwd);
+  a.ws_chain = plan->ws_chain;
+  a.l = (int)d.num_layers;
+  a.b = (int)d.block_size;
+  a.ne = (int)d.num_energies;
+  return rgfk::launch_rgf_lesser(a, static_cast<hipStream_t>(stream)) == hipSuccess ? RGF_OK : RGF_ERR_HIP;
+}
+
 rgf_status_t ddrgf_solve(rgf_plan_t plan, const void* H, const void* sigma_L, const void* sigma_R,
                          const double* energies, double eta_d, void* G, double* T, int32_t* info,
                          void* workspace, size_t workspace_bytes, void* stream) {
@@ -562,6 +591,41 @@ rgf_status_t rgf_plan_workspace_bytes(rgf_plan_t plan, size_t* workspace_bytes) 
   if (!plan || !workspace_bytes) return RGF_ERR_INVALID_ARG;
   *workspace_bytes = plan->ws_bytes;
   return RGF_OK;
+}
+
+rgf_status_t rgf_lead_workspace_bytes(int64_t block_size, int64_t num_energies, size_t* workspace_bytes) {
+  if (!workspace_bytes || block_size < 1 || num_energies < 1) return RGF_ERR_INVALID_ARG;
+  if (block_size > 128 || num_energies > (int64_t)1 << 24) return RGF_ERR_UNSUPPORTED;
+  const int bp = rgfk::padded_block((int)block_size);
+  *workspace_bytes = rgfk::lead_ws_chain_elems(bp) * sizeof(double2) * (size_t)num_energies;
+  return RGF_OK;
+}
+
+rgf_status_t rgf_lead_self_energy(int64_t block_size, int64_t num_energies, const void* H00, const void* H01,
+                                  const void* Hc, const double* energies, double eta, double tolerance,
+                                  int32_t max_steps, void* sigma, int32_t* steps, void* workspace,
+                                  size_t workspace_bytes, void* stream) {
+  size_t need = 0;
+  rgf_status_t st = rgf_lead_workspace_bytes(block_size, num_energies, &need);
+  if (st != RGF_OK) return st;
+  if (!H00 || !H01 || !Hc || !energies || !sigma || !steps) return RGF_ERR_INVALID_ARG;
+  if (!(tolerance > 0.0) || max_steps < 1 || !(eta >= 0.0)) return RGF_ERR_INVALID_ARG;
+  if (!workspace || workspace_bytes < need) return RGF_ERR_WORKSPACE_TOO_SMALL;
+  rgfk::LeadArgs a{};
+  a.H00 = static_cast<const double2*>(H00);
+  a.H01 = static_cast<const double2*>(H01);
+  a.Hc = static_cast<const double2*>(Hc);
+  a.E = energies;
+  a.eta = eta;
+  a.tol = tolerance;
+  a.max_steps = max_steps;
+  a.sigma = static_cast<double2*>(sigma);
+  a.steps = steps;
+  a.ws = static_cast<double2*>(workspace);
+  a.ws_chain = rgfk::lead_ws_chain_elems(rgfk::padded_block((int)block_size));
+  a.b = (int)block_size;
+  a.ne = (int)num_energies;
+  return rgfk::launch_lead_decimation(a, static_cast<hipStream_t>(stream)) == hipSuccess ? RGF_OK : RGF_ERR_HIP;
 }
 
 rgf_status_t rgf_plan_set_split(rgf_plan_t plan, int32_t workgroups_per_energy, int64_t spin_limit) {

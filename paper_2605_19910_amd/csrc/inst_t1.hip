@@ -6,3 +6,5 @@
 #include "nrgf_sweep.hip"
 #include "adjoint.hip"
 #include "rgf_split.hip"
+#include "lesser.hip"
+#include "leads.hip"

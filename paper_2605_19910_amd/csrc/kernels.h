@@ -113,6 +113,42 @@ size_t ddrgf_interior_ws_elems(int nmax, int bp);
 void ddrgf_layout_host(int l, int m, int* base, int* rem);
 hipError_t launch_ddrgf(const DDArgs& a, hipStream_t s);
 
+// Lesser Green's function on the band after a sequential w = 1 FP64 sweep
+// (lesser.hip); reuses the sweep's per-energy workspace.
+struct LesserArgs {
+  const double2* sigL;       // [ne][b][b]
+  const double2* sigR;
+  const double* fL;          // [ne] occupation of the left lead
+  const double* fR;          // [ne] occupation of the right lead
+  const double2* G;          // band of G^R [ne][3][l][b][b] written by the sweep
+  const int* info;           // [ne] the sweep's status
+  double2* Gless;            // out band of G^< [ne][3][l][b][b]
+  double2* ws;               // the sweep's workspace, ws_chain elements per energy
+  size_t ws_chain;
+  int l, b, ne;
+};
+
+hipError_t launch_rgf_lesser(const LesserArgs& a, hipStream_t s);
+
+// Lead self-energies by decimation (leads.hip), one workgroup per energy.
+struct LeadArgs {
+  const double2* H00;        // [b][b] on-layer block of the lead
+  const double2* H01;        // [b][b] coupling to the next layer away from the device
+  const double2* Hc;         // [b][b] coupling from the device layer to the lead's surface
+  const double* E;           // [ne]
+  double eta;
+  double tol;
+  int max_steps;
+  double2* sigma;            // out [ne][b][b]
+  int* steps;                // out [ne]
+  double2* ws;               // ws_chain elements per energy
+  size_t ws_chain;
+  int b, ne;
+};
+
+size_t lead_ws_chain_elems(int bp);
+hipError_t launch_lead_decimation(const LeadArgs& a, hipStream_t s);
+
 // Persistent batched launch (see rgf_batched_kernel).
 struct BatchArgs {
   const rgf_batch_device_t* devs;   // device table [n_dev]

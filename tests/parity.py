@@ -205,12 +205,26 @@ def task_mixed(spec):
     return {"G": r["G"], "T": oracle.transmission(r["G_0_last"], a[2], a[3]), "kappa": float("nan")}
 
 
+def task_lesser(spec):
+    """spec: (src, e, eta_d, (f_L, f_R)); the band of G^< and the sweep's kappa."""
+    import oracle
+    src, e, eta_d, occ = spec
+    wl, a = _args(src, e, eta_d)
+    G, Gl = oracle.lesser(*a[:4], occ[0], occ[1], a[4])
+    r = oracle.rgf(*a, extras=False, pivot_cond=True)
+    return {"G": Gl, "GR": G, "kappa": r["pivot_cond"]}
+
+
 TASKS = {"rgf": task_rgf, "nrgf": task_nrgf, "ddrgf": task_ddrgf, "ext": task_ext, "dense": task_dense,
-         "mixed": task_mixed}
+         "mixed": task_mixed, "lesser": task_lesser}
 
 
-def oracle_results(kind: str, src, energies, eta_d=None, m=None):
+def oracle_results(kind: str, src, energies, eta_d=None, m=None, occ=None):
+    """occ (kind "lesser"): per energy (f_L, f_R)."""
     fn = TASKS[kind]
+    if kind == "lesser":
+        specs = [(src, int(e), eta_d, tuple(o)) for e, o in zip(energies, occ)]
+        return pmap(fn, specs)
     specs = [(src, int(e), eta_d, m) if kind == "ddrgf" else (src, int(e), eta_d) for e in energies]
     return pmap(fn, specs)
 

@@ -130,6 +130,45 @@ def test_backward_plan_workspace_and_mismatch():
         binding.Plan(8, 4, 1, 1, want_backward=4)
 
 
+def test_lesser_and_lead_argument_errors():
+    """Host-side checks of the lesser and lead entry points (no HIP call is made)."""
+    binding = _lib()
+    lib = binding.load()
+    size = ctypes.c_size_t(0)
+    assert lib.rgf_lead_workspace_bytes(16, 3, ctypes.byref(size)) == 0
+    assert size.value == 8 * 16 * 16 * 16 * 3
+    assert lib.rgf_lead_workspace_bytes(0, 3, ctypes.byref(size)) == 1
+    assert lib.rgf_lead_workspace_bytes(129, 3, ctypes.byref(size)) == 2
+    assert lib.rgf_lead_workspace_bytes(16, 3, None) == 1
+    dummy = ctypes.c_void_p(16)
+    # null pointers, bad tolerance / steps / eta, small workspace
+    assert lib.rgf_lead_self_energy(4, 1, None, dummy, dummy, dummy, 1e-3, 1e-14, 10, dummy, dummy, dummy, 1 << 20,
+                                    None) == 1
+    assert lib.rgf_lead_self_energy(4, 1, dummy, dummy, dummy, dummy, 1e-3, 0.0, 10, dummy, dummy, dummy, 1 << 20,
+                                    None) == 1
+    assert lib.rgf_lead_self_energy(4, 1, dummy, dummy, dummy, dummy, 1e-3, 1e-14, 0, dummy, dummy, dummy, 1 << 20,
+                                    None) == 1
+    assert lib.rgf_lead_self_energy(4, 1, dummy, dummy, dummy, dummy, -1.0, 1e-14, 10, dummy, dummy, dummy, 1 << 20,
+                                    None) == 1
+    assert lib.rgf_lead_self_energy(4, 1, dummy, dummy, dummy, dummy, 1e-3, 1e-14, 10, dummy, dummy, dummy, 16,
+                                    None) == 4
+    # lesser: DDRGF plan -> plan mismatch; mixed / backward plans -> unsupported; null occupations
+    f = [dummy] * 4
+    p = binding.Plan(8, 4, 1, 1, method="ddrgf", domains=2)
+    assert lib.rgf_solve_lesser(p.handle, *f, 0.0, dummy, dummy, dummy, dummy, dummy, dummy, dummy, 1 << 20,
+                                None) == 6
+    p.close()
+    for kw in (dict(precision="fp32"), dict(want_backward=True)):
+        p = binding.Plan(8, 4, 1, 1, **kw)
+        assert lib.rgf_solve_lesser(p.handle, *f, 0.0, dummy, dummy, dummy, dummy, dummy, dummy, dummy, 1 << 20,
+                                    None) == 2
+        p.close()
+    p = binding.Plan(8, 4, 1, 1)
+    assert lib.rgf_solve_lesser(p.handle, *f, 0.0, None, dummy, dummy, dummy, dummy, dummy, dummy, 1 << 20,
+                                None) == 1
+    p.close()
+
+
 def test_split_arguments():
     """Workgroups per energy: 0, 1, 2, 4 accepted, anything else and negative spin
     limits rejected on the host; before any solve the plan reports 1."""
