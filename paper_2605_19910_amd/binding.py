@@ -304,6 +304,9 @@ def solve(H, sigma_L, sigma_R, energies, eta_d: float = 0.0, method: str = "rgf"
           precision: str = "fp64", domains: int = 0, want_transmission: bool = True,
           plan: Optional[Plan] = None, workspace=None, out=None) -> Tuple:
     """Allocate outputs (torch, on H's device) and run one solve on the current stream.
+    method "auto" times the sequential sweep and DDRGF with each admissible domain
+    count on these inputs once per workload signature and uses the fastest
+    (paper_2605_19910_amd.dispatch).
 
     H: complex128 [2w+1, l, b, b]; sigma_L, sigma_R: complex128 [nE, b, b];
     energies: float64 [nE].  Returns (G [nE, 2w+1, l, b, b], T [nE], info [nE])."""
@@ -317,6 +320,12 @@ def solve(H, sigma_L, sigma_R, energies, eta_d: float = 0.0, method: str = "rgf"
     if energies.dtype != torch.float64 or not energies.is_cuda:
         raise ValueError("energies must be a float64 GPU tensor")
     if plan is None:
+        if method == "auto":
+            # measured choice between the sequential sweep and DDRGF, cached per workload
+            from . import dispatch
+            rec = dispatch.choose(l, b, w, ne, dispatch.gpu_measure(H, sigma_L, sigma_R, energies, eta_d, precision),
+                                  precision=precision, device=f"cuda{H.device.index or 0}")
+            method, domains = rec["method"], rec["domains"]
         plan = Plan(l, b, w, ne, method=method, precision=precision, domains=domains,
                     want_transmission=want_transmission)
     dev = H.device

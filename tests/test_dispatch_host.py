@@ -1,0 +1,50 @@
+"""Host logic of the measured method choice (no GPU): admissible candidates,
+tie-breaking, and the per-signature cache."""
+import pytest
+
+from paper_2605_19910_amd import dispatch
+
+
+def test_candidates():
+    c = dispatch.candidates(256, 128, 1, "fp64")
+    assert c[0] == ("rgf", 0)
+    assert [m for k, m in c if k == "ddrgf"] == [2, 4, 8, 16, 32]
+    # w = 2: super-blocks of w b must fit 128, l divisible by w, interiors >= w layers
+    assert [m for k, m in dispatch.candidates(512, 64, 2, "fp64") if k == "ddrgf"] == [2, 4, 8, 16, 32]
+    assert dispatch.candidates(512, 100, 2, "fp64") == [("rgf", 0)]
+    assert dispatch.candidates(511, 64, 2, "fp64") == [("rgf", 0)]
+    assert [m for k, m in dispatch.candidates(10, 8, 1, "fp64") if k == "ddrgf"] == [2, 4]
+    # mixed precision: sequential only; methods filter
+    assert dispatch.candidates(256, 128, 1, "fp32") == [("rgf", 0)]
+    assert dispatch.candidates(256, 128, 1, "fp64", methods=("ddrgf",))[0] == ("ddrgf", 2)
+
+
+def test_pick_ties():
+    assert dispatch.pick({("ddrgf", 8): 1.0, ("rgf", 0): 1.0}) == ("rgf", 0)
+    assert dispatch.pick({("ddrgf", 8): 1.0, ("ddrgf", 4): 1.0}) == ("ddrgf", 4)
+    assert dispatch.pick({("ddrgf", 8): 0.5, ("rgf", 0): 1.0}) == ("ddrgf", 8)
+
+
+def test_choose_caches(tmp_path, monkeypatch):
+    monkeypatch.setattr(dispatch, "TABLE", str(tmp_path / "table.json"))
+    monkeypatch.setattr(dispatch, "_cache", {})
+    calls = []
+
+    def measure(method, m):
+        calls.append((method, m))
+        return {"rgf": 10.0}.get(method, 20.0 - m)
+
+    rec = dispatch.choose(40, 32, 1, 8, measure)
+    assert (rec["method"], rec["domains"]) == ("ddrgf", 16)
+    n = len(calls)
+    assert n == len(dispatch.candidates(40, 32, 1))
+    again = dispatch.choose(40, 32, 1, 8, measure)
+    assert again == rec and len(calls) == n
+    # persisted: a fresh process (empty memory cache) reads the table
+    monkeypatch.setattr(dispatch, "_cache", {})
+    assert dispatch.choose(40, 32, 1, 8, measure) == rec and len(calls) == n
+    # restricted choice is a different signature
+    rec2 = dispatch.choose(40, 32, 1, 8, measure, methods=("rgf",))
+    assert rec2["method"] == "rgf"
+    with pytest.raises(ValueError):
+        dispatch.choose(40, 32, 1, 8, measure, precision="fp32", methods=("ddrgf",))
