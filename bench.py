@@ -33,13 +33,15 @@ HBM_PEAK_GBS = 8000.0
 # known size.  Valid only for the kernel sources the counters were taken on: their sha256
 # is stored with the figure, and a mismatch reports null.
 TRAFFIC_SOURCES = ("paper_2605_19910_amd/csrc/block_engine.h", "paper_2605_19910_amd/csrc/kernels.h",
-                   "paper_2605_19910_amd/csrc/ddrgf.hip", "paper_2605_19910_amd/csrc/rgf_sweep.hip")
+                   "paper_2605_19910_amd/csrc/ddrgf.hip", "paper_2605_19910_amd/csrc/rgf_sweep.hip",
+                   "paper_2605_19910_amd/csrc/split_engine.h", "paper_2605_19910_amd/csrc/rgf_split.hip")
 MEASURED_TRAFFIC = {
-    # DDRGF interior kernel, l=256, b=128, 64 energies, 8 domains: FETCH_SIZE 6.4352e+07 KiB x 2.00
-    # + WRITE_SIZE 5.0856e+07 KiB x 1.00 (copy calibration: 1 GiB copy reads 5.2431e+05, writes 1.0486e+06 KiB)
-    ("ddrgf_interior_kernel", "c2/ddrgf_fp64"): {
-        "sha256": "5d43c3204608ca478e8097c0d1049b20054c3daf4c7e7a09bdf4926ddfb9aa11",
-        "bytes": 1.838642e+11},
+    # sequential sweep with 4 workgroups per energy, l=256, b=128, 64 energies: FETCH_SIZE
+    # 2.77269e+07 KiB x 2.00 + WRITE_SIZE 3.40461e+07 KiB x 1.00 (copy calibration: a 1 GiB copy
+    # reads 5.2431e+05 and writes 1.0486e+06 KiB); profiles/rgf_split_kernel_b128_l256_e64_counters.txt
+    ("rgf_split_kernel", "c2/rgf_fp64"): {
+        "sha256": "5711b1c0fdbbd74f513e2e16babffea83c6ed0410a7e481ff1c91554b763d911",
+        "bytes": 9.164560e+10},
 }
 
 
