@@ -22,7 +22,7 @@ Band layout: H[w + k, i] is block (i, i + k); the same layout is used for output
 from __future__ import annotations
 
 from dataclasses import dataclass, field
-from typing import Callable, Dict, List, Optional
+from typing import Callable, Dict, List, Optional, Sequence
 
 import numpy as np
 import scipy.linalg as sla
@@ -454,8 +454,19 @@ def domain_layout(l: int, n_pairs: int, s1: int):
 
 
 def ddrgf(H, w, E, sigma_L, sigma_R, eta_d=0.0, n_pairs=2, s1: Optional[int] = None,
-          drop_orange: bool = False, return_parts: bool = False, pivot_cond: bool = False):
-    """Single-level DDRGF (Algorithm 2), block n-diagonal, separators of s1 = w layers.
+          drop_orange: bool = False, return_parts: bool = False, pivot_cond: bool = False,
+          inner_pairs: Sequence[int] = ()):
+    """DDRGF (Algorithm 2) of M(E) = (E + i eta_d) I - H - Sigma; see ddrgf_blocks."""
+    l, b = H.shape[1], H.shape[2]
+    Mb = block_accessor(H, w, E, sigma_L, sigma_R, eta_d)
+    return ddrgf_blocks(Mb, l, b, w, n_pairs, s1, drop_orange, return_parts, pivot_cond, inner_pairs)
+
+
+def ddrgf_blocks(Mb: Callable[[int, int], Optional[np.ndarray]], l: int, b: int, w: int, n_pairs=2,
+                 s1: Optional[int] = None, drop_orange: bool = False, return_parts: bool = False,
+                 pivot_cond: bool = False, inner_pairs: Sequence[int] = ()):
+    """DDRGF (Algorithm 2), block n-diagonal, separators of s1 = w layers, on the
+    blocks returned by Mb.
 
     Step 1: for every interior D2^k, X^(k) = (M_{D2^k})^{-1} restricted to the band
             plus its first/last w block rows and columns (extended RGF).
@@ -470,8 +481,13 @@ def ddrgf(H, w, E, sigma_L, sigma_R, eta_d=0.0, n_pairs=2, s1: Optional[int] = N
             G_{D1,D2} = -G_S T_12 X,  G_{D2,D2} = X + X T_21 G_S T_12 X,
             each only inside the band.
     Step 5: everything is written straight into natural layer order.
+
+    Multi-level (the recursion of Algorithm 2's step 3): with ``inner_pairs`` =
+    (m2, m3, ...) the reduced system is itself solved by DDRGF with m2 pairs (its
+    own reduced system with m3 pairs, and so on), and by RGF at the last level.
+    The outer level needs from the reduced inverse only its band and the block
+    (first separator, last separator), which DDRGF returns as G_0_last.
     """
-    l, b = H.shape[1], H.shape[2]
     if s1 is None:
         s1 = w
     if s1 != w:
@@ -481,7 +497,6 @@ def ddrgf(H, w, E, sigma_L, sigma_R, eta_d=0.0, n_pairs=2, s1: Optional[int] = N
     for (a, e, p) in lay:
         if e - a + 1 < w:
             raise ValueError("interiors must hold at least w layers")
-    Mb = block_accessor(H, w, E, sigma_L, sigma_R, eta_d)
     wb = w * b
 
     def dense(rows: List[int], cols: List[int]) -> np.ndarray:
@@ -565,9 +580,15 @@ def ddrgf(H, w, E, sigma_L, sigma_R, eta_d=0.0, n_pairs=2, s1: Optional[int] = N
             return S_lo[j]
         return None
 
-    red = nrgf(Sb, m, wb, 1, halo=1, pivot_cond=pivot_cond)
-    GS = red["G"]                       # [3, m, wb, wb]
-    GS_first_row = red["first_rows"][0]  # [m, wb, wb]: G_S(0, k)
+    if inner_pairs:
+        # multi-level: the reduced (block tridiagonal, w b blocks) system by DDRGF
+        red = ddrgf_blocks(Sb, m, wb, 1, inner_pairs[0], None, False, False, pivot_cond, tuple(inner_pairs[1:]))
+        GS = red["G"]
+        GS_0_last = red["G_0_last"]
+    else:
+        red = nrgf(Sb, m, wb, 1, halo=1, pivot_cond=pivot_cond)
+        GS = red["G"]                                # [3, m, wb, wb]
+        GS_0_last = red["first_rows"][0][m - 1]      # G_S(0, m-1)
 
     def gs(i, j):
         if i == j:
@@ -576,8 +597,8 @@ def ddrgf(H, w, E, sigma_L, sigma_R, eta_d=0.0, n_pairs=2, s1: Optional[int] = N
             return GS[2, i]
         if i == j + 1:
             return GS[0, i]
-        if i == 0:
-            return GS_first_row[j]
+        if i == 0 and j == m - 1:
+            return GS_0_last
         raise KeyError((i, j))
 
     # ---- Steps 4 and 5 ------------------------------------------------------

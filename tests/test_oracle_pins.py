@@ -384,6 +384,27 @@ def test_ddrgf_equals_rgf(l, b, w, m):
         assert rel(bad["G"], ref["G"]) > 1e-3
 
 
+ML_CASES = [(40, 4, 1, 8, (2,)), (64, 3, 1, 16, (4, 2)), (48, 5, 2, 6, (2,)), (33, 6, 1, 8, (3,)),
+            (80, 2, 1, 20, (5, 2))]
+
+
+@pytest.mark.parametrize("l,b,w,m,inner", ML_CASES)
+def test_multilevel_ddrgf_equals_rgf(l, b, w, m, inner):
+    """Multi-level DDRGF (the reduced system solved by DDRGF again, down to RGF at the
+    last level): the same band and first-to-last block as RGF and the dense inverse."""
+    wl = make_random(l, b, w, 2, seed=500 + l, eta=1e-3)
+    for e in range(wl.ne):
+        args = (wl.H, w, wl.energies[e], wl.sigma_L[e], wl.sigma_R[e], 0.05)
+        ref = O.nrgf(O.block_accessor(*args), l, b, w, halo=1)
+        d = O.ddrgf(*args, n_pairs=m, inner_pairs=inner)
+        one = O.ddrgf(*args, n_pairs=m)
+        assert rel(d["G"], O.dense_selected(*args)) < 1e-12
+        assert rel(d["G"], ref["G"]) < 1e-12
+        assert rel(d["G_0_last"], ref["first_rows"][0, l - 1]) < 1e-12
+        # and the single-level result
+        assert rel(d["G"], one["G"]) < 1e-12
+
+
 @pytest.mark.parametrize("l,b,w,m", DD_CASES)
 def test_ddrgf_without_broadening_within_pivot_bound(l, b, w, m):
     """With eta_d = 0 a closed interior can have a nearly singular Schur pivot even when
