@@ -113,6 +113,10 @@ typedef struct {
   int64_t checkpoint_domains;/* rgf_backward: layers are cut into this many domains (0 = 8) */
   double mixed_tolerance;    /* RGF_MIXED_FP32: largest kappa_1(S_i) * 2^-24 run with FP32
                                 products (0 = 1e-5, the mixed-precision error target) */
+  int64_t inner_domains;     /* DDRGF, FP64: 0 = the reduced separator system is solved by the
+                                sequential sweep; m2 >= 1 = by DDRGF with m2 pairs (two-level
+                                recursion of Algorithm 2's step 3); needs num_domains >= 2 m2
+                                (counted in w-layer groups for w > 1) */
 } rgf_desc_t;
 
 /* Validate a description and build a plan.  *workspace_bytes receives the size of

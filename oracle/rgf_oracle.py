@@ -582,7 +582,8 @@ def ddrgf_blocks(Mb: Callable[[int, int], Optional[np.ndarray]], l: int, b: int,
 
     if inner_pairs:
         # multi-level: the reduced (block tridiagonal, w b blocks) system by DDRGF
-        red = ddrgf_blocks(Sb, m, wb, 1, inner_pairs[0], None, False, False, pivot_cond, tuple(inner_pairs[1:]))
+        red = ddrgf_blocks(Sb, m, wb, 1, inner_pairs[0], None, False, return_parts, pivot_cond,
+                           tuple(inner_pairs[1:]))
         GS = red["G"]
         GS_0_last = red["G_0_last"]
     else:
@@ -672,6 +673,8 @@ def ddrgf_blocks(Mb: Callable[[int, int], Optional[np.ndarray]], l: int, b: int,
         out["pivot_cond"] = max([x["pivot_cond"] for x in X] + [red["pivot_cond"]])
     if return_parts:
         out.update(X=X, S_diag=S_diag, S_up=S_up, S_lo=S_lo, GS=GS, layout=lay)
+        if inner_pairs:
+            out["inner"] = red
     return out
 
 

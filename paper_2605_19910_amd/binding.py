@@ -40,6 +40,7 @@ class RgfDesc(ctypes.Structure):
         ("want_backward", ctypes.c_int32),
         ("checkpoint_domains", ctypes.c_int64),
         ("mixed_tolerance", ctypes.c_double),
+        ("inner_domains", ctypes.c_int64),
     ]
 
 
@@ -133,12 +134,13 @@ class Plan:
 
     def __init__(self, l: int, b: int, w: int, ne: int, method: str = "rgf", precision: str = "fp64",
                  domains: int = 0, separator_layers: int = 0, want_transmission: bool = True,
-                 want_backward: bool = False, checkpoint_domains: int = 0, mixed_tolerance: float = 0.0):
+                 want_backward: bool = False, checkpoint_domains: int = 0, mixed_tolerance: float = 0.0,
+                 inner_domains: int = 0):
         self.lib = load()
         wb = int(want_backward) if not isinstance(want_backward, bool) else (BACKWARD_ONSITE if want_backward else 0)
         self.desc = RgfDesc(l, b, w, ne, PRECISION[precision], METHOD[method], domains,
                             separator_layers, 1 if want_transmission else 0, wb,
-                            checkpoint_domains, float(mixed_tolerance))
+                            checkpoint_domains, float(mixed_tolerance), int(inner_domains))
         self.handle = _VP()
         ws = ctypes.c_size_t(0)
         st = self.lib.rgf_plan_create(ctypes.byref(self.desc), ctypes.byref(self.handle), ctypes.byref(ws))

@@ -493,6 +493,27 @@ __device__ __forceinline__ void add_identity(Acc<T, NW>& acc) {
     }
 }
 
+// acc += I on the diagonal entries with index >= b (the padding of a b x b block).
+template <int T, int NW>
+__device__ __forceinline__ void add_identity_beyond(Acc<T, NW>& acc, int b) {
+  constexpr int RR = Acc<T, NW>::RR;
+  constexpr int RC = Acc<T, NW>::RC;
+  const int l = lane_id();
+  int tr0, tc0;
+  tile_origin<T, NW>(tr0, tc0);
+#pragma unroll
+  for (int r = 0; r < RR; ++r)
+#pragma unroll
+    for (int c = 0; c < RC; ++c) {
+      if (tr0 + r >= T || tc0 + c >= T) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 16 * (tr0 + r) + c_row(l, v), j = 16 * (tc0 + c) + c_col(l);
+        if (i == j && i >= b) acc.re[r][c][v] += 1.0;
+      }
+    }
+}
+
 // Pivot-search key of a row whose candidate has magnitude k (k < 0: non-finite):
 // unpivoted rows rank above pivoted rows and lanes without a row (key 0),
 // non-finite candidates below finite ones; finite ones by the top 57 bits of k,

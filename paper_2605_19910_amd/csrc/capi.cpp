@@ -28,6 +28,11 @@ struct rgf_plan_s {
   // DDRGF workspace layout (byte offsets)
   size_t dd_int_chain, dd_red_chain;
   size_t off_int, off_ms, off_gs, off_gsrow, off_red, off_fin, off_info, off_herm;
+  // second DDRGF level (inner_domains > 0): its interiors, reduced band, inverse band and
+  // first row, sweep workspace, finalize scratch, status, and the inner form of the band
+  size_t dd2_int_chain = 0, dd2_red_chain = 0;
+  size_t off2_int = 0, off2_ms = 0, off2_gs = 0, off2_gsrow = 0, off2_red = 0, off2_fin = 0, off2_info = 0,
+         off2_band = 0;
   // w > 1 DDRGF: super-block copies of the inputs and of the output band
   int fl, fb;                    // super-layers and super-block size of the DDRGF system
   size_t off_hf, off_slf, off_srf, off_gf, off_inff;
@@ -118,6 +123,11 @@ rgf_status_t validate(const rgf_desc_t* d) {
     if (d->method != RGF_METHOD_SEQUENTIAL || d->half_bandwidth != 1 || d->precision != RGF_FP64)
       return RGF_ERR_UNSUPPORTED;
     if (d->checkpoint_domains < 0) return RGF_ERR_INVALID_ARG;
+  }
+  if (d->inner_domains != 0) {
+    if (d->inner_domains < 0 || d->method != RGF_METHOD_DDRGF) return RGF_ERR_INVALID_ARG;
+    if (d->precision != RGF_FP64) return RGF_ERR_UNSUPPORTED;
+    if (d->num_domains < 2 * d->inner_domains) return RGF_ERR_INVALID_ARG;
   }
   if (d->method == RGF_METHOD_DDRGF) {
     const int64_t w = d->half_bandwidth;
@@ -218,6 +228,21 @@ rgf_status_t rgf_plan_create(const rgf_desc_t* desc, rgf_plan_t* plan, size_t* w
     p->off_fin = off;   off = align256(off + (size_t)ne * 4 * bpbp * sizeof(double2));
     p->off_info = off;  off = align256(off + (size_t)ne * (m + 1) * sizeof(int));
     p->off_herm = off;  off = align256(off + sizeof(int));
+    if (desc->inner_domains > 0) {
+      const int m2 = (int)desc->inner_domains;
+      int base2 = 0, rem2 = 0;
+      rgfk::ddrgf_layout_host(m, m2, &base2, &rem2);
+      p->dd2_int_chain = rgfk::ddrgf_interior_ws_elems(base2 + 1, p->bp);
+      p->dd2_red_chain = rgfk::sweep_ws_chain_elems(m2, p->bp);
+      p->off2_int = off;   off = align256(off + p->dd2_int_chain * sizeof(double2) * (size_t)ne * m2);
+      p->off2_ms = off;    off = align256(off + (size_t)ne * 3 * m2 * bb * sizeof(double2));
+      p->off2_gs = off;    off = align256(off + (size_t)ne * 3 * m2 * bb * sizeof(double2));
+      p->off2_gsrow = off; off = align256(off + (size_t)ne * m2 * bb * sizeof(double2));
+      p->off2_red = off;   off = align256(off + p->dd2_red_chain * sizeof(double2) * (size_t)ne);
+      p->off2_fin = off;   off = align256(off + (size_t)ne * 4 * bpbp * sizeof(double2));
+      p->off2_info = off;  off = align256(off + (size_t)ne * (m2 + 1) * sizeof(int));
+      p->off2_band = off;  off = align256(off + (size_t)ne * 3 * m * bb * sizeof(double2));
+    }
     if (w > 1) {
       p->off_hf = off;   off = align256(off + (size_t)3 * l * bb * sizeof(double2));
       p->off_slf = off;  off = align256(off + (size_t)ne * bb * sizeof(double2));
@@ -541,7 +566,40 @@ rgf_status_t ddrgf_solve(rgf_plan_t plan, const void* H, const void* sigma_L, co
   a.herm = reinterpret_cast<int*>(ws + plan->off_herm);
   a.mixed = d.precision == RGF_MIXED_FP32 ? 1 : 0;
   a.kappa_max = kappa_limit(d.mixed_tolerance);
-  hipError_t e = rgfk::launch_ddrgf(a, st);
+  rgfk::DDArgs a2{};
+  double2* band2 = nullptr;
+  if (d.inner_domains > 0) {
+    // second level: DDRGF on the reduced separator system of every energy
+    const int m = a.m, m2 = (int)d.inner_domains;
+    const size_t bb = (size_t)a.b * a.b;
+    band2 = reinterpret_cast<double2*>(ws + plan->off2_band);
+    a2.H = band2;
+    a2.direct = 1;
+    a2.h_stride = (size_t)3 * m * bb;
+    a2.G = a.GS;
+    a2.T = nullptr;
+    a2.info = a.info_part;
+    a2.info_stride = m + 1;
+    a2.info_offset = m;
+    a2.first_last = a.GSrow + (size_t)(m - 1) * bb;
+    a2.first_last_stride = (size_t)m * bb;
+    a2.l = m;
+    a2.b = a.b;
+    a2.m = m2;
+    a2.ne = a.ne;
+    a2.ws_int = reinterpret_cast<double2*>(ws + plan->off2_int);
+    a2.ws_int_chain = plan->dd2_int_chain;
+    a2.MS = reinterpret_cast<double2*>(ws + plan->off2_ms);
+    a2.GS = reinterpret_cast<double2*>(ws + plan->off2_gs);
+    a2.GSrow = reinterpret_cast<double2*>(ws + plan->off2_gsrow);
+    a2.ws_red = reinterpret_cast<double2*>(ws + plan->off2_red);
+    a2.ws_red_chain = plan->dd2_red_chain;
+    a2.ws_fin = reinterpret_cast<double2*>(ws + plan->off2_fin);
+    a2.info_part = reinterpret_cast<int*>(ws + plan->off2_info);
+    a2.herm = nullptr;
+    a2.mixed = 0;
+  }
+  hipError_t e = rgfk::launch_ddrgf(a, d.inner_domains > 0 ? &a2 : nullptr, band2, st);
   if (e == hipSuccess && w > 1) e = rgfk::launch_unfuse(f, st);
   return e == hipSuccess ? RGF_OK : RGF_ERR_HIP;
 }

@@ -82,9 +82,17 @@ __global__ void herm_check_kernel(const double2* H, int l, int b, int* flag) {
 #endif
 
 // Diagonal block of M for global layer i: (E + i eta) I - H_ii - [i==0] Sigma_L - [i==l-1] Sigma_R.
+// In direct mode (inner levels) the diagonal block is read as it is, with the
+// identity on the padding.
 template <int T, int NW>
 __device__ __forceinline__ void diag_M(Acc<T, NW>& acc, const DDArgs& a, int e, int i, bool add = false) {
   const size_t bb = (size_t)a.b * a.b;
+  if (a.direct) {
+    if (!add) acc_zero<T, NW>(acc);
+    add_from<T, NW>(acc, opnd(a.H + (size_t)(a.l + i) * bb, a.b, a.b, a.b));
+    add_identity_beyond<T, NW>(acc, a.b);
+    return;
+  }
   const double2 z = make_double2(a.E[e], a.eta_d);
   assemble_diag<T, NW>(acc, a.H + (size_t)(a.l + i) * bb, a.b, z,
                        i == 0 ? a.sigL + (size_t)e * bb : nullptr,
@@ -325,6 +333,7 @@ template <int T, int NW, int MIXED>
 __global__ __launch_bounds__(64 * NW, 1) void ddrgf_interior_kernel(DDArgs a) {
   __shared__ GJShared sh;
   const int c = blockIdx.x;
+  a.H += (size_t)(c / a.m) * a.h_stride;
   if (!MIXED && herm_interior(a, c % a.m))
     interior_herm<T, NW, MIXED>(a, c, sh);
   else
@@ -339,6 +348,7 @@ __global__ __launch_bounds__(64 * NW, 1) void ddrgf_schur_kernel(DDArgs a) {
   constexpr int BP = 16 * T;
   const int c = blockIdx.x;
   const int e = c / a.m, k = c % a.m;
+  a.H += (size_t)e * a.h_stride;
   const DDLayout lay = dd_layout(a.l, a.m);
   const int b = a.b, m = a.m;
   const size_t bb = (size_t)b * b, bpbp = (size_t)BP * BP;
@@ -378,6 +388,7 @@ __global__ __launch_bounds__(64 * NW, 1) void ddrgf_recover_kernel(DDArgs a) {
   constexpr int BP = 16 * T;
   const int c = blockIdx.x;
   const int e = c / a.m, k = c % a.m;
+  a.H += (size_t)e * a.h_stride;
   const DDLayout lay = dd_layout(a.l, a.m);
   const int n = lay.n(k), a0 = lay.a(k), qR = lay.p(k), qL = a0 - 1;
   const int b = a.b, m = a.m;
@@ -499,7 +510,8 @@ __global__ __launch_bounds__(64 * NW, 1) void ddrgf_finalize_kernel(DDArgs a) {
   double2* GamR = scr + 2 * bpbp;
   double2* X1 = scr + 3 * bpbp;
   double Tval = 0.0;
-  if (a.T) {
+  if (a.T || a.first_last) {
+    // block (0, l-1) of the inverse: -(X^(0) T21)_{0, D1^0} G_S(0, m-1)
     const double2* CR0 = a.ws_int + (size_t)(e * m) * a.ws_int_chain + (size_t)6 * nmax * bpbp;
     const double2* GS = a.GS + (size_t)e * 3 * m * bb;
     const double2* GSrow = a.GSrow + (size_t)e * m * bb;
@@ -508,9 +520,11 @@ __global__ __launch_bounds__(64 * NW, 1) void ddrgf_finalize_kernel(DDArgs a) {
     acc_zero<T, NW>(acc);
     mma<T, NW>(acc, opnd(CR0, BP, BP, BP), opnd(Z, b, b, b), -1.0);
     store<T, NW>(acc, G0L, BP, BP, BP);
+    if (a.first_last) store<T, NW>(acc, a.first_last + (size_t)e * a.first_last_stride, b, b, b);
     __syncthreads();
-    Tval = transmission<T, NW>(acc, G0L, a.sigL + (size_t)e * bb, a.sigR + (size_t)e * bb, b, GamL, GamR,
-                               X1, red);
+    if (a.T)
+      Tval = transmission<T, NW>(acc, G0L, a.sigL + (size_t)e * bb, a.sigR + (size_t)e * bb, b, GamL, GamR,
+                                 X1, red);
   }
   if (inf != 0) {
     const double qnan = __builtin_nan("");
@@ -520,12 +534,25 @@ __global__ __launch_bounds__(64 * NW, 1) void ddrgf_finalize_kernel(DDArgs a) {
   }
   if (t == 0) {
     if (a.T) a.T[e] = Tval;
-    a.info[e] = inf;
+    a.info[(size_t)e * (a.info_stride > 0 ? a.info_stride : 1) + a.info_offset] = inf;
+  }
+}
+
+// Band of a reduced separator system (the band of M itself) to the form an inner
+// DDRGF level reads: diagonal blocks as they are, off-diagonal blocks negated.
+// (A template so that every block-size translation unit that launches it has it.)
+template <int D = 0>
+__global__ void reduced_to_inner_kernel(const double2* MS, double2* out, size_t n, size_t band_elems,
+                                        size_t diag_lo, size_t diag_hi) {
+  for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < n; idx += (size_t)gridDim.x * blockDim.x) {
+    const size_t r = idx % band_elems;
+    const double2 x = MS[idx];
+    out[idx] = (r >= diag_lo && r < diag_hi) ? x : make_double2(-x.x, -x.y);
   }
 }
 
 template <int T>
-hipError_t launch_dd_T(const DDArgs& a, hipStream_t s) {
+hipError_t launch_dd_T(const DDArgs& a, const DDArgs* inner, double2* inner_band, hipStream_t s) {
   constexpr int NW = T >= 7 ? 8 : 4;
   const int chains = a.ne * a.m;
   if (a.mixed)
@@ -538,6 +565,15 @@ hipError_t launch_dd_T(const DDArgs& a, hipStream_t s) {
   hipLaunchKernelGGL((ddrgf_schur_kernel<T, NW>), dim3(chains), dim3(64 * NW), 0, s, a);
   if ((err = hipGetLastError()) != hipSuccess) return err;
   ktime_mark("ddrgf_schur_kernel", s);
+  if (inner) {
+    // multi-level: the reduced system by DDRGF again (its status, band and block
+    // (first separator, last separator) land where the sweep would put them)
+    const size_t bb = (size_t)a.b * a.b, band = (size_t)3 * a.m * bb;
+    hipLaunchKernelGGL(reduced_to_inner_kernel<0>, dim3(1024), dim3(256), 0, s, a.MS, inner_band, band * a.ne, band,
+                       (size_t)a.m * bb, (size_t)2 * a.m * bb);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    if ((err = launch_dd_T<T>(*inner, nullptr, nullptr, s)) != hipSuccess) return err;
+  } else {
   SweepArgs r{};
   r.H = a.MS;
   r.h_stride = (size_t)3 * a.m * a.b * a.b;
@@ -557,6 +593,7 @@ hipError_t launch_dd_T(const DDArgs& a, hipStream_t s) {
   r.mixed = a.mixed;
   r.kappa_max = a.kappa_max;
   if ((err = launch_rgf_sweep(r, s)) != hipSuccess) return err;
+  }
   if (a.mixed)
     hipLaunchKernelGGL((ddrgf_recover_kernel<T, NW, 1>), dim3(chains), dim3(64 * NW), 0, s, a);
   else
@@ -570,19 +607,28 @@ hipError_t launch_dd_T(const DDArgs& a, hipStream_t s) {
 }
 
 #ifdef RGFK_INST_T
-template hipError_t launch_dd_T<RGFK_INST_T>(const DDArgs& a, hipStream_t s);
+template hipError_t launch_dd_T<RGFK_INST_T>(const DDArgs& a, const DDArgs* inner, double2* inner_band,
+                                             hipStream_t s);
 #else
-extern template hipError_t launch_dd_T<1>(const DDArgs& a, hipStream_t s);
-extern template hipError_t launch_dd_T<2>(const DDArgs& a, hipStream_t s);
-extern template hipError_t launch_dd_T<3>(const DDArgs& a, hipStream_t s);
-extern template hipError_t launch_dd_T<4>(const DDArgs& a, hipStream_t s);
-extern template hipError_t launch_dd_T<5>(const DDArgs& a, hipStream_t s);
-extern template hipError_t launch_dd_T<6>(const DDArgs& a, hipStream_t s);
-extern template hipError_t launch_dd_T<7>(const DDArgs& a, hipStream_t s);
-extern template hipError_t launch_dd_T<8>(const DDArgs& a, hipStream_t s);
+extern template hipError_t launch_dd_T<1>(const DDArgs& a, const DDArgs* inner, double2* inner_band,
+                                                   hipStream_t s);
+extern template hipError_t launch_dd_T<2>(const DDArgs& a, const DDArgs* inner, double2* inner_band,
+                                                   hipStream_t s);
+extern template hipError_t launch_dd_T<3>(const DDArgs& a, const DDArgs* inner, double2* inner_band,
+                                                   hipStream_t s);
+extern template hipError_t launch_dd_T<4>(const DDArgs& a, const DDArgs* inner, double2* inner_band,
+                                                   hipStream_t s);
+extern template hipError_t launch_dd_T<5>(const DDArgs& a, const DDArgs* inner, double2* inner_band,
+                                                   hipStream_t s);
+extern template hipError_t launch_dd_T<6>(const DDArgs& a, const DDArgs* inner, double2* inner_band,
+                                                   hipStream_t s);
+extern template hipError_t launch_dd_T<7>(const DDArgs& a, const DDArgs* inner, double2* inner_band,
+                                                   hipStream_t s);
+extern template hipError_t launch_dd_T<8>(const DDArgs& a, const DDArgs* inner, double2* inner_band,
+                                                   hipStream_t s);
 
-hipError_t launch_ddrgf(const DDArgs& a, hipStream_t s) {
-  if (a.herm) {
+hipError_t launch_ddrgf(const DDArgs& a, const DDArgs* inner, double2* inner_band, hipStream_t s) {
+  if (a.herm && !a.direct) {
     hipLaunchKernelGGL(herm_flag_init_kernel, dim3(1), dim3(64), 0, s, a.herm);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
@@ -591,14 +637,14 @@ hipError_t launch_ddrgf(const DDArgs& a, hipStream_t s) {
     ktime_mark("herm_check_kernel", s);
   }
   switch (padded_block(a.b) / 16) {
-    case 1: return launch_dd_T<1>(a, s);
-    case 2: return launch_dd_T<2>(a, s);
-    case 3: return launch_dd_T<3>(a, s);
-    case 4: return launch_dd_T<4>(a, s);
-    case 5: return launch_dd_T<5>(a, s);
-    case 6: return launch_dd_T<6>(a, s);
-    case 7: return launch_dd_T<7>(a, s);
-    case 8: return launch_dd_T<8>(a, s);
+    case 1: return launch_dd_T<1>(a, inner, inner_band, s);
+    case 2: return launch_dd_T<2>(a, inner, inner_band, s);
+    case 3: return launch_dd_T<3>(a, inner, inner_band, s);
+    case 4: return launch_dd_T<4>(a, inner, inner_band, s);
+    case 5: return launch_dd_T<5>(a, inner, inner_band, s);
+    case 6: return launch_dd_T<6>(a, inner, inner_band, s);
+    case 7: return launch_dd_T<7>(a, inner, inner_band, s);
+    case 8: return launch_dd_T<8>(a, inner, inner_band, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -107,11 +107,20 @@ struct DDArgs {
   int mixed;                 // 1: products on FP32 MFMA, FP64 pivots + one refinement step
   double kappa_max;          // as SweepArgs::kappa_max (reduced system)
   int* herm;                 // device flag: H exactly Hermitian (set by the check kernel)
+  // multi-level DDRGF (the inner levels solve a reduced separator system):
+  int direct;                // 1: the diagonal blocks of H hold M_ii itself (no E, eta_d, Sigma
+                             //    added); the off-diagonal blocks hold -M_ij as those of H do
+  size_t h_stride;           // elements between the bands of consecutive energies (0: H shared)
+  double2* first_last;       // optional out: block (0, l-1) of the inverse of energy e at
+  size_t first_last_stride;  //   first_last + e * first_last_stride (b x b)
+  int info_stride, info_offset;   // status of energy e at info[e * stride + offset] (stride 0: 1)
 };
 
 size_t ddrgf_interior_ws_elems(int nmax, int bp);
 void ddrgf_layout_host(int l, int m, int* base, int* rem);
-hipError_t launch_ddrgf(const DDArgs& a, hipStream_t s);
+// inner: the next level's arguments (its H is inner_band, filled here from a.MS), or
+// null to solve the reduced system by the sequential sweep.
+hipError_t launch_ddrgf(const DDArgs& a, const DDArgs* inner, double2* inner_band, hipStream_t s);
 
 // Lesser Green's function on the band after a sequential w = 1 FP64 sweep
 // (lesser.hip); reuses the sweep's per-energy workspace.

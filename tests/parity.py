@@ -169,13 +169,28 @@ def task_nrgf(spec):
 
 
 def task_ddrgf(spec):
+    """spec: (src, e, eta_d, m) with m the number of pairs, or (m, m2, ...) for
+    multi-level DDRGF.  Returns the band, T, kappa_max over every level, and the
+    DDRGF rule's n_int and rho (for several levels: the largest interior over the
+    levels and the product of the levels' rho)."""
     import oracle
     src, e, eta_d, m = spec
+    inner = ()
+    if isinstance(m, (tuple, list)):
+        m, inner = m[0], tuple(m[1:])
     wl, a = _args(src, e, eta_d)
-    r = oracle.ddrgf(wl.H, wl.w, *a[1:], n_pairs=m, pivot_cond=True, return_parts=True)
-    xn = np.sqrt(sum(np.linalg.norm(x["G"]) ** 2 for x in r["X"]))
-    rho = xn / np.linalg.norm(mask_band(r["G"], wl.w))
-    n_int = wl.b * max(e1 - a1 + 1 for (a1, e1, p1) in r["layout"])
+    r = oracle.ddrgf(wl.H, wl.w, *a[1:], n_pairs=m, pivot_cond=True, return_parts=True, inner_pairs=inner)
+    rho, n_int = 1.0, 0
+    lev, band, blk = r, mask_band(r["G"], wl.w), wl.b
+    while True:
+        xn = np.sqrt(sum(np.linalg.norm(x["G"]) ** 2 for x in lev["X"]))
+        rho *= max(1.0, xn / np.linalg.norm(band))
+        n_int = max(n_int, blk * max(e1 - a1 + 1 for (a1, e1, p1) in lev["layout"]))
+        if "inner" not in lev:
+            break
+        blk = wl.w * wl.b
+        band = mask_band(lev["GS"], 1)
+        lev = lev["inner"]
     return {"G": r["G"], "T": oracle.transmission(r["G_0_last"], a[2], a[3]), "kappa": r["pivot_cond"],
             "rho": rho, "n_int": n_int}
 

@@ -77,6 +77,9 @@ def test_plan_workspace_size(l, b, w, ne):
     (dict(l=8, b=4, w=1, ne=1, method="ddrgf", domains=2, want_backward=True), 2),
     (dict(l=8, b=4, w=1, ne=1, precision="fp32", want_backward=True), 2),
     (dict(l=8, b=4, w=1, ne=1, precision="fp32", mixed_tolerance=-1.0), 1),
+    (dict(l=8, b=4, w=1, ne=1, inner_domains=1), 1),
+    (dict(l=16, b=4, w=1, ne=1, method="ddrgf", domains=4, inner_domains=3), 1),
+    (dict(l=16, b=4, w=1, ne=1, method="ddrgf", domains=4, inner_domains=-1), 1),
 ])
 def test_plan_validation_errors(args, code):
     binding = _lib()
