@@ -327,9 +327,11 @@ def solve(H, sigma_L, sigma_R, energies, eta_d: float = 0.0, method: str = "rgf"
             from . import dispatch
             rec = dispatch.choose(l, b, w, ne, dispatch.gpu_measure(H, sigma_L, sigma_R, energies, eta_d, precision),
                                   precision=precision, device=f"cuda{H.device.index or 0}")
-            method, domains = rec["method"], rec["domains"]
+            method, domains, inner = rec["method"], rec["domains"], rec.get("inner_domains", 0)
+        else:
+            inner = 0
         plan = Plan(l, b, w, ne, method=method, precision=precision, domains=domains,
-                    want_transmission=want_transmission)
+                    want_transmission=want_transmission, inner_domains=inner)
     dev = H.device
     if out is None:
         G = torch.empty((ne, nb, l, b, b), dtype=torch.complex128, device=dev)

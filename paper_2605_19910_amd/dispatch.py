@@ -31,11 +31,13 @@ def signature(l: int, b: int, w: int, ne: int, precision: str, device: str) -> s
 
 
 def candidates(l: int, b: int, w: int, precision: str = "fp64",
-               methods: Iterable[str] = ("rgf", "ddrgf")) -> List[Tuple[str, int]]:
-    """Admissible (method, domains) pairs: the sequential sweep, and DDRGF (FP64 only)
-    with separators of w layers and interiors of at least w layers; for w > 1 the
-    w-layer super-blocks must fit the kernels (l divisible by w, w b <= 128)."""
-    out: List[Tuple[str, int]] = []
+               methods: Iterable[str] = ("rgf", "ddrgf")) -> List[Tuple]:
+    """Admissible candidates: ("rgf", 0), the sequential sweep; ("ddrgf", m), DDRGF
+    (FP64 only) with separators of w layers and interiors of at least w layers (for
+    w > 1 the w-layer super-blocks must fit the kernels: l divisible by w, w b <= 128);
+    ("ddrgf", m, m2), two-level DDRGF with m2 inner pairs, for m >= 16 and
+    m2 in {2, 4, 8} with m >= 2 m2."""
+    out: List[Tuple] = []
     if "rgf" in methods:
         out.append(("rgf", 0))
     if "ddrgf" in methods and precision == "fp64":
@@ -45,12 +47,15 @@ def candidates(l: int, b: int, w: int, precision: str = "fp64",
             if w > 1 and (l % w != 0 or w * b > 128 or l // w - m < m):
                 continue
             out.append(("ddrgf", m))
+            if m >= 16:
+                out += [("ddrgf", m, m2) for m2 in (2, 4, 8) if m >= 2 * m2]
     return out
 
 
-def pick(timings: Dict[Tuple[str, int], float]) -> Tuple[str, int]:
-    """Fastest candidate; ties go to the sequential sweep, then to fewer domains."""
-    return min(timings, key=lambda k: (timings[k], 0 if k[0] == "rgf" else 1, k[1]))
+def pick(timings: Dict[Tuple, float]) -> Tuple:
+    """Fastest candidate; ties go to the sequential sweep, then to fewer levels and
+    fewer domains."""
+    return min(timings, key=lambda k: (timings[k], 0 if k[0] == "rgf" else 1, len(k), k[1:]))
 
 
 def _load_table() -> dict:
@@ -80,11 +85,12 @@ def lookup(sig: str) -> Optional[dict]:
         return rec
 
 
-def choose(l: int, b: int, w: int, ne: int, measure: Callable[[str, int], float], precision: str = "fp64",
+def choose(l: int, b: int, w: int, ne: int, measure: Callable[..., float], precision: str = "fp64",
            device: str = "cuda0", methods: Iterable[str] = ("rgf", "ddrgf"), retune: bool = False,
            persist: bool = True) -> dict:
-    """Time every candidate with measure(method, domains) -> milliseconds and keep the
-    fastest.  Returns {"method", "domains", "timings_ms"}; cached per signature."""
+    """Time every candidate with measure(method, domains[, inner_domains]) ->
+    milliseconds and keep the fastest.  Returns {"method", "domains",
+    "inner_domains", "timings_ms"}; cached per signature."""
     methods = tuple(methods)
     sig = signature(l, b, w, ne, precision, device) + "_" + "+".join(sorted(methods))
     if not retune:
@@ -95,9 +101,9 @@ def choose(l: int, b: int, w: int, ne: int, measure: Callable[[str, int], float]
     if not cands:
         raise ValueError("no admissible method for this workload")
     timings = {c: float(measure(*c)) for c in cands}
-    method, m = pick(timings)
-    rec = {"method": method, "domains": m,
-           "timings_ms": {f"{k[0]}/{k[1]}": round(v, 4) for k, v in timings.items()}}
+    best = pick(timings)
+    rec = {"method": best[0], "domains": best[1], "inner_domains": best[2] if len(best) > 2 else 0,
+           "timings_ms": {"/".join(str(x) for x in k): round(v, 4) for k, v in timings.items()}}
     with _lock:
         _cache[sig] = rec
     if persist:
@@ -106,7 +112,7 @@ def choose(l: int, b: int, w: int, ne: int, measure: Callable[[str, int], float]
 
 
 def gpu_measure(H, sigma_L, sigma_R, energies, eta_d: float = 0.0, precision: str = "fp64",
-                reps: int = 2) -> Callable[[str, int], float]:
+                reps: int = 2) -> Callable[..., float]:
     """measure() for choose(): one untimed solve, then the summed kernel time of the
     best of reps solves, from the library's events on the launch stream."""
     import torch
@@ -116,8 +122,8 @@ def gpu_measure(H, sigma_L, sigma_R, energies, eta_d: float = 0.0, precision: st
     w = (nb - 1) // 2
     ne = energies.shape[0]
 
-    def measure(method: str, m: int) -> float:
-        plan = binding.Plan(l, b, w, ne, method=method, precision=precision, domains=m)
+    def measure(method: str, m: int, m2: int = 0) -> float:
+        plan = binding.Plan(l, b, w, ne, method=method, precision=precision, domains=m, inner_domains=m2)
         ws = torch.empty((plan.workspace_bytes,), dtype=torch.uint8, device=H.device)
         G = torch.empty((ne, nb, l, b, b), dtype=torch.complex128, device=H.device)
         T = torch.empty((ne,), dtype=torch.float64, device=H.device)

@@ -8,12 +8,14 @@ from paper_2605_19910_amd import dispatch
 def test_candidates():
     c = dispatch.candidates(256, 128, 1, "fp64")
     assert c[0] == ("rgf", 0)
-    assert [m for k, m in c if k == "ddrgf"] == [2, 4, 8, 16, 32]
+    assert [x[1] for x in c if x[0] == "ddrgf" and len(x) == 2] == [2, 4, 8, 16, 32]
+    assert [x[1:] for x in c if len(x) == 3] == [(16, 2), (16, 4), (16, 8), (32, 2), (32, 4), (32, 8)]
     # w = 2: super-blocks of w b must fit 128, l divisible by w, interiors >= w layers
-    assert [m for k, m in dispatch.candidates(512, 64, 2, "fp64") if k == "ddrgf"] == [2, 4, 8, 16, 32]
+    assert [x[1] for x in dispatch.candidates(512, 64, 2, "fp64") if len(x) == 2 and x[0] == "ddrgf"] == \
+        [2, 4, 8, 16, 32]
     assert dispatch.candidates(512, 100, 2, "fp64") == [("rgf", 0)]
     assert dispatch.candidates(511, 64, 2, "fp64") == [("rgf", 0)]
-    assert [m for k, m in dispatch.candidates(10, 8, 1, "fp64") if k == "ddrgf"] == [2, 4]
+    assert [x[1] for x in dispatch.candidates(10, 8, 1, "fp64") if x[0] == "ddrgf"] == [2, 4]
     # mixed precision: sequential only; methods filter
     assert dispatch.candidates(256, 128, 1, "fp32") == [("rgf", 0)]
     assert dispatch.candidates(256, 128, 1, "fp64", methods=("ddrgf",))[0] == ("ddrgf", 2)
@@ -23,6 +25,7 @@ def test_pick_ties():
     assert dispatch.pick({("ddrgf", 8): 1.0, ("rgf", 0): 1.0}) == ("rgf", 0)
     assert dispatch.pick({("ddrgf", 8): 1.0, ("ddrgf", 4): 1.0}) == ("ddrgf", 4)
     assert dispatch.pick({("ddrgf", 8): 0.5, ("rgf", 0): 1.0}) == ("ddrgf", 8)
+    assert dispatch.pick({("ddrgf", 16, 2): 1.0, ("ddrgf", 16): 1.0}) == ("ddrgf", 16)
 
 
 def test_choose_caches(tmp_path, monkeypatch):
@@ -30,9 +33,9 @@ def test_choose_caches(tmp_path, monkeypatch):
     monkeypatch.setattr(dispatch, "_cache", {})
     calls = []
 
-    def measure(method, m):
-        calls.append((method, m))
-        return {"rgf": 10.0}.get(method, 20.0 - m)
+    def measure(method, m, m2=0):
+        calls.append((method, m, m2))
+        return {"rgf": 10.0}.get(method, 20.0 - m + 0.5 * m2)
 
     rec = dispatch.choose(40, 32, 1, 8, measure)
     assert (rec["method"], rec["domains"]) == ("ddrgf", 16)

@@ -30,13 +30,15 @@ def test_auto_small(lib, table):
     rec = table._cache[sig]
     print(f"auto choice for 40 x 32, 4 energies: {rec}", flush=True)
     best = min(rec["timings_ms"].values())
-    assert rec["timings_ms"][f"{rec['method']}/{rec['domains']}"] == best
+    key = f"{rec['method']}/{rec['domains']}" + (f"/{rec['inner_domains']}" if rec["inner_domains"] else "")
+    assert rec["timings_ms"][key] == best
     assert bool((info == 0).all())
     Gn, Tn = G.cpu().numpy(), T.cpu().numpy()
     if rec["method"] == "rgf":
         check_fp64("auto", Gn, Tn, range(4), oracle_results("rgf", wl, range(4)), 1, 32)
     else:
-        check_dd("auto", Gn, Tn, range(4), oracle_results("ddrgf", wl, range(4), m=rec["domains"]),
+        m = (rec["domains"], rec["inner_domains"]) if rec["inner_domains"] else rec["domains"]
+        check_dd("auto", Gn, Tn, range(4), oracle_results("ddrgf", wl, range(4), m=m),
                  oracle_results("dense", wl, range(4)), 1)
     # a second call reuses the choice (no new measurements)
     before = dict(table._cache)
@@ -53,7 +55,8 @@ def test_auto_config2_choice(lib, table):
     rec = table.choose(wl.l, wl.b, wl.w, wl.ne, meas, persist=False)
     print(f"auto choice for configuration 2: {rec}", flush=True)
     t = rec["timings_ms"]
-    assert "rgf/0" in t and "ddrgf/8" in t
-    assert t[f"{rec['method']}/{rec['domains']}"] == min(t.values())
+    assert "rgf/0" in t and "ddrgf/8" in t and "ddrgf/32/4" in t
+    key = f"{rec['method']}/{rec['domains']}" + (f"/{rec['inner_domains']}" if rec["inner_domains"] else "")
+    assert t[key] == min(t.values())
     torch.cuda.synchronize()
     free_gpu()

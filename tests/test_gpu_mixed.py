@@ -108,6 +108,44 @@ def test_mixed_batched_small(lib):
                         info.cpu().numpy(), range(wl.ne), refs_d, wl.b)
 
 
+def test_mixed_batched_config4(lib):
+    """The 64-device batched workload with FP32 products: every instance either kept
+    FP32 products (then within the mixed target) or was recomputed with FP64
+    products (flagged, then within the FP64 rule); the longest device of each block
+    size at two energies against the oracle, and every T finite and in [0, b]."""
+    import torch
+    from parity import pmap, task_rgf
+    wls = make_config(4)
+    outs = lib.solve_batched(to_dev_batch(wls), 0.0, precision="fp32")
+    torch.cuda.synchronize()
+    infos = [o[2].cpu().numpy() for o in outs]
+    assert all(np.all(i & 0x3FFFFFFF == 0) for i in infos)
+    n_fp32 = sum(int(np.sum((i & FLAG) == 0)) for i in infos)
+    print(f"config4 mixed: {n_fp32} of {sum(len(i) for i in infos)} instances kept FP32 products", flush=True)
+    for wl, o in zip(wls, outs):
+        T = o[1].cpu().numpy()
+        assert np.all(np.isfinite(T)) and np.all(T >= -1e-5) and np.all(T <= wl.b + 1e-5)
+    pick = {}
+    for d, w in enumerate(wls):
+        if w.b not in pick or w.l > wls[pick[w.b]].l:
+            pick[w.b] = d
+    items = [(d, e) for b, d in sorted(pick.items()) for e in (3, 12)]
+    refs = pmap(task_rgf, [(("config", 4, d), e, None) for d, e in items])
+    bad = []
+    for (d, e), r in zip(items, refs):
+        wl = wls[d]
+        fell_back = bool(infos[d][e] & FLAG)
+        err = rel(outs[d][0][e].cpu().numpy(), r["G"][1])
+        te = terr(outs[d][1][e].item(), r["T"])
+        tol = fp64_bound(r["kappa"], wl.b) if fell_back else TARGET_MIXED
+        print(f"config4 mixed device {d} (l={wl.l}, b={wl.b}) energy {e}: kappa {r['kappa']:.2e} "
+              f"{'FP64 products' if fell_back else 'mixed'} |dG_ii|/|G_ii| {err:.2e} dT {te:.2e} bound {tol:.2e}",
+              flush=True)
+        if not (err <= tol and te <= tol):
+            bad.append((d, e, err, te, tol))
+    assert not bad, bad
+
+
 def test_mixed_ddrgf_rejected(lib):
     """Mixed DDRGF is refused: the closed interiors' pivots are ill-conditioned at
     most energies of these generators (every interior would fall back to FP64)."""
