@@ -175,8 +175,9 @@ rgf_status_t rgf_lead_self_energy(int64_t block_size, int64_t num_energies, cons
                                   size_t workspace_bytes, void* stream);
 
 /* Several workgroups per energy for rgf_solve.  With fewer energies than compute
- * units, the sequential sweep of Algorithm 1 (w = 1, FP64, plans without
- * want_backward, padded block size 64 or 128) can give each energy K = 2 or 4
+ * units, the sequential sweep (Algorithm 1 for w = 1, the n-diagonal sweep of Sec.
+ * 2.3 for w > 1; FP64, plans without want_backward, padded block size 64 or 128)
+ * can give each energy K = 2 or 4
  * workgroups: each computes a row slab of every block product, the first also
  * inverts the Schur pivots, and they meet at bounded group barriers (cooperative
  * launch, so all are resident).  Results are bitwise those of one workgroup per

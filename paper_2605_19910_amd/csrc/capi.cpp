@@ -148,8 +148,7 @@ rgf_status_t validate(const rgf_desc_t* d) {
 // Workgroups per energy for a plain sequential solve on this stream's device.
 int split_for(rgf_plan_s* p, hipStream_t st) {
   const rgf_desc_t& d = p->d;
-  if (d.half_bandwidth != 1 || d.method != RGF_METHOD_SEQUENTIAL || d.precision != RGF_FP64 ||
-      d.want_backward || p->split_want == 1)
+  if (d.method != RGF_METHOD_SEQUENTIAL || d.precision != RGF_FP64 || d.want_backward || p->split_want == 1)
     return 1;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return 1;
@@ -157,7 +156,9 @@ int split_for(rgf_plan_s* p, hipStream_t st) {
   if (hipGetDevice(&dev) != hipSuccess) return 1;
   std::lock_guard<std::mutex> lock(p->mu);
   if (p->split_k < 0 || p->split_dev != dev) {
-    p->split_k = rgfk::split_workgroups((int)d.block_size, (int)d.num_energies, p->split_want);
+    p->split_k = d.half_bandwidth == 1
+                     ? rgfk::split_workgroups((int)d.block_size, (int)d.num_energies, p->split_want)
+                     : rgfk::split_workgroups_n((int)d.block_size, (int)d.num_energies, p->split_want);
     p->split_dev = dev;
   }
   return p->split_k;
@@ -182,7 +183,7 @@ rgf_status_t rgf_plan_create(const rgf_desc_t* desc, rgf_plan_t* plan, size_t* w
   else
     p->ws_chain = rgfk::nrgf_ws_chain_elems((int)desc->num_layers, w, p->bp);
   p->ws_bytes = p->ws_chain * sizeof(double2) * (size_t)desc->num_energies;
-  if (w == 1 && desc->method == RGF_METHOD_SEQUENTIAL && !desc->want_backward) {
+  if (desc->method == RGF_METHOD_SEQUENTIAL && !desc->want_backward) {
     // group counters of the split sweep, 64 bytes per energy
     p->off_sync = align256(p->ws_bytes);
     p->ws_bytes = p->off_sync + (size_t)64 * desc->num_energies;
@@ -434,7 +435,19 @@ rgf_status_t rgf_solve(rgf_plan_t plan, const void* H, const void* sigma_L, cons
     n.b = (int)d.block_size;
     n.w = (int)d.half_bandwidth;
     n.ne = (int)d.num_energies;
-    hipError_t e = rgfk::launch_nrgf_sweep(n, static_cast<hipStream_t>(stream));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int K = split_for(plan, st);
+    if (K > 1) {
+      n.sync = reinterpret_cast<unsigned*>(static_cast<char*>(workspace) + plan->off_sync);
+      n.spin_limit = plan->split_spin > 0 ? plan->split_spin : DEFAULT_SPLIT_SPIN;
+      if (rgfk::launch_nrgf_split(n, K, st) == hipSuccess) {
+        plan->split_used = K;
+        return RGF_OK;
+      }
+      (void)hipGetLastError();
+    }
+    plan->split_used = 1;
+    hipError_t e = rgfk::launch_nrgf_sweep(n, st);
     return e == hipSuccess ? RGF_OK : RGF_ERR_HIP;
   }
   rgfk::SweepArgs a{};

@@ -8,3 +8,4 @@
 #include "rgf_split.hip"
 #include "lesser.hip"
 #include "leads.hip"
+#include "nrgf_split.hip"

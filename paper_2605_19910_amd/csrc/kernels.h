@@ -189,9 +189,15 @@ struct NSweepArgs {
   double2* ws;
   size_t ws_chain;
   int l, b, w, ne;
+  unsigned* sync;            // split sweep: one group counter per energy, 64 bytes apart
+  long long spin_limit;      // split sweep: polls before a group barrier gives up
 };
 
 size_t nrgf_ws_chain_elems(int l, int w, int bp);
+// n-diagonal sweep with K workgroups per energy (nrgf_split.hip), FP64, padded block
+// size 64 or 128; K from split_workgroups_n (as split_workgroups).
+int split_workgroups_n(int b, int ne, int want);
+hipError_t launch_nrgf_split(const NSweepArgs& a, int K, hipStream_t s);
 hipError_t launch_nrgf_sweep(const NSweepArgs& a, hipStream_t s);
 
 // Super-block view (w layers -> one layer of w*b orbitals) of a band and its leads.

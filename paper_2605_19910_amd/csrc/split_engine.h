@@ -147,9 +147,9 @@ __device__ __forceinline__ void sstore(const SAcc<TR, TC, NW>& acc, double2* p, 
   }
 }
 
-// acc = X[slab] (operand view of the whole block)
+// acc = sgn * X[slab] (operand view of the whole block)
 template <int TR, int TC, int NW>
-__device__ __forceinline__ void sload(SAcc<TR, TC, NW>& acc, const Opnd& X, int row0) {
+__device__ __forceinline__ void sload(SAcc<TR, TC, NW>& acc, const Opnd& X, int row0, double sgn = 1.0) {
   using S = SAcc<TR, TC, NW>;
   const int l = lane_id();
   int tr0, tc0;
@@ -163,8 +163,8 @@ __device__ __forceinline__ void sload(SAcc<TR, TC, NW>& acc, const Opnd& X, int 
       for (int v = 0; v < 4; ++v) {
         const int i = row0 + 16 * (tr0 + r) + c_row(l, v);
         const double2 x = (tr0 + r < TR && tc0 + c < TC) ? opnd_get(X, i, j) : make_double2(0.0, 0.0);
-        acc.re[r][c][v] = x.x;
-        acc.im[r][c][v] = x.y;
+        acc.re[r][c][v] = sgn * x.x;
+        acc.im[r][c][v] = sgn * x.y;
       }
     }
 }

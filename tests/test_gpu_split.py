@@ -17,10 +17,10 @@ pytestmark = pytest.mark.gpu
 TIMEOUT = 0x20000000
 
 
-def solve_k(lib, dev_inputs, l, b, ne, k, spin=0):
+def solve_k(lib, dev_inputs, l, b, ne, k, spin=0, w=1):
     import torch
     H, sL, sR, E = dev_inputs
-    plan = lib.Plan(l, b, 1, ne)
+    plan = lib.Plan(l, b, w, ne)
     plan.set_split(k, spin)
     G, T, info = lib.solve(H, sL, sR, E, eta_d=0.0, plan=plan)
     torch.cuda.synchronize()
@@ -29,11 +29,11 @@ def solve_k(lib, dev_inputs, l, b, ne, k, spin=0):
     return G, T, info, used
 
 
-def same(lib, a, b):
+def same(lib, a, b, w=1):
     import torch
     Ga, Ta, ia = a[:3]
     Gb, Tb, ib = b[:3]
-    return (np.array_equal(mask_band(Ga.cpu().numpy(), 1), mask_band(Gb.cpu().numpy(), 1))
+    return (np.array_equal(mask_band(Ga.cpu().numpy(), w), mask_band(Gb.cpu().numpy(), w))
             and torch.equal(Ta, Tb) and torch.equal(ia, ib))
 
 
@@ -57,6 +57,46 @@ def test_split_bitwise_equal(lib, l, b, ne):
     assert bool((info == 0).all())
     check_fp64(f"split l={l} b={b}", G.cpu().numpy(), T.cpu().numpy(), range(min(ne, 3)),
                oracle_results("rgf", wl, range(min(ne, 3))), 1, b)
+
+
+@pytest.mark.parametrize("l,b,w,ne", [(20, 64, 2, 6), (33, 120, 2, 3), (17, 50, 3, 5), (4, 128, 3, 2)])
+def test_split_ndiagonal_bitwise_equal(lib, l, b, w, ne):
+    """The n-diagonal sweep with 2 and 4 workgroups per energy: bitwise the
+    one-workgroup sweep, and within the FP64 rule of the oracle."""
+    from parity import oracle_results as orc
+    wl = make_random(l, b, w, ne, seed=3500 + l + b + w, eta=1e-3)
+    d = to_dev(wl)
+    ref = solve_k(lib, d, l, b, ne, 1, w=w)
+    for k in (2, 4):
+        out = solve_k(lib, d, l, b, ne, k, w=w)
+        print(f"n-diagonal split l={l} b={b} w={w} ne={ne}: asked {k}, used {out[3]}", flush=True)
+        assert out[3] == k
+        assert same(lib, out, ref, w), (l, b, w, k)
+    G, T, info = ref[:3]
+    assert bool((info == 0).all())
+    check_fp64(f"n-diagonal split l={l} b={b} w={w}", G.cpu().numpy(), T.cpu().numpy(), range(min(ne, 2)),
+               orc("nrgf", wl, range(min(ne, 2))), w, b)
+
+
+def test_split_config3_all_energies(lib):
+    """The pentadiagonal 512 x 64 system over its 128 energies: several workgroups per
+    energy give bitwise the one-workgroup results."""
+    import torch
+    wl = make_config(3)
+    d = to_dev(wl)
+    ref = solve_k(lib, d, wl.l, wl.b, wl.ne, 1, w=2)
+    out = solve_k(lib, d, wl.l, wl.b, wl.ne, 0, w=2)
+    print(f"config3: {out[3]} workgroups per energy", flush=True)
+    assert out[3] in (2, 4)
+    for G in (out[0], ref[0]):
+        for kk in range(-2, 3):
+            if kk < 0:
+                G[:, 2 + kk, :(-kk)] = 0
+            elif kk > 0:
+                G[:, 2 + kk, wl.l - kk:] = 0
+    assert torch.equal(out[0], ref[0]) and torch.equal(out[1], ref[1]) and torch.equal(out[2], ref[2])
+    del out, ref
+    free_gpu()
 
 
 def test_split_singular_pivot(lib):
@@ -123,8 +163,7 @@ def test_split_timeout_reported(lib):
 
 
 def test_split_not_used_for_other_plans(lib):
-    """Mixed precision, adjoint checkpoints, DDRGF and w > 1 keep one workgroup per
-    energy."""
+    """Mixed precision and adjoint checkpoints keep one workgroup per energy."""
     import torch
     wl = make_random(8, 64, 1, 2, seed=9, eta=1e-3)
     H, sL, sR, E = to_dev(wl)
