@@ -1,0 +1,6 @@
+// Persistent batched kernel, FP64 products, 8 waves per workgroup: a
+// translation unit of its own so that the variants build in parallel.
+#define RGFK_BATCHED_TU
+#define RGFK_BMIXED 0
+#define RGFK_BNW 8
+#include "rgf_sweep.hip"

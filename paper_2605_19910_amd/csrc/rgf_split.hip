@@ -4,8 +4,9 @@
 // Workgroup k of a group owns the row slab [k bp/K, (k+1) bp/K) of every block
 // product of the chain (split_engine.h); workgroup 0 also inverts each Schur pivot
 // (the Gauss-Jordan inverse needs the whole block and stays on one compute unit).
-// Per layer of the upward pass: inverse on workgroup 0 | barrier | L_i, U_i slabs |
-// barrier | S_{i-1} slab | barrier; per layer of the downward pass: G_{i-1,i},
+// Per layer of the upward pass: inverse on workgroup 0 (the other workgroups compute
+// the previous layer's U_{i+1} meanwhile) | barrier | L_i slabs | barrier | S_{i-1}
+// slab | barrier; per layer of the downward pass: G_{i-1,i},
 // G_{i,i-1}, R_i slabs | barrier | G_ii slab | barrier.  Blocks another workgroup
 // reads go through the chain's workspace; the slabs of one block never overlap.
 // The arithmetic of every output element is that of the one-workgroup sweep, so
@@ -78,6 +79,13 @@ __global__ __launch_bounds__(64 * NW, 1) void rgf_split_kernel(SweepArgs a) {
     sadd_diag<TR, T, NW>(sa, Hd + (size_t)(l - 1) * bb, b, z, l == 1 ? sL : nullptr, sR, row0);
     sstore<TR, T, NW>(sa, Sbuf, BP, BP, BP, row0);
     if (!bar()) return false;
+    // U_{i+1} = M_{i,i+1} g_{i+1} is needed only by the downward pass: its slabs are
+    // computed by workgroups 1..K-1 while workgroup 0 inverts the next pivot
+    // (workgroup 1 also takes workgroup 0's slab).
+    auto u_slab = [&](int i1, int slab) {
+      sgemm<TR, T, NW>(sa, Pn(Hu + (size_t)(i1 - 1) * bb), P(g + (size_t)i1 * bpbp), ms, 16 * TR * slab);
+      sstore<TR, T, NW>(sa, U + (size_t)i1 * bpbp, BP, BP, BP, 16 * TR * slab);
+    };
     for (int i = l - 1; i >= 0; --i) {
       double2* gi = g + (size_t)i * bpbp;
       if (leader) {
@@ -85,13 +93,14 @@ __global__ __launch_bounds__(64 * NW, 1) void rgf_split_kernel(SweepArgs a) {
         load<T, NW>(acc, P(Sbuf));
         gj_invert<T, NW>(acc, gi, sh);
         if (sh.bad && bad_layer < 0) bad_layer = i;
+      } else if (i + 1 < l) {
+        u_slab(i + 1, k);
+        if (k == 1) u_slab(i + 1, 0);
       }
       if (!bar()) return false;
       if (i == 0) break;
       sgemm<TR, T, NW>(sa, P(gi), Pn(Hl + (size_t)i * bb), ms, row0);
       sstore<TR, T, NW>(sa, L + (size_t)i * bpbp, BP, BP, BP, row0);
-      sgemm<TR, T, NW>(sa, Pn(Hu + (size_t)(i - 1) * bb), P(gi), ms, row0);
-      sstore<TR, T, NW>(sa, U + (size_t)i * bpbp, BP, BP, BP, row0);
       if (!bar()) return false;
       // S_{i-1} = M_{i-1,i-1} - M_{i-1,i} L_i
       sgemm<TR, T, NW>(sa, Pn(Hu + (size_t)(i - 1) * bb), P(L + (size_t)i * bpbp), -ms, row0);

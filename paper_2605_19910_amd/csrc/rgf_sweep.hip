@@ -337,6 +337,12 @@ hipError_t launch_rgf_sweep(const SweepArgs& a, hipStream_t s) {
 // workgroup owns one workspace slot sized for the largest chain.  NW (4 or 8 waves
 // per workgroup, two or one workgroups per compute unit) is the plan's tile choice.
 // ---------------------------------------------------------------------------
+// One translation unit per (MIXED, NW) variant of the kernel (they build in
+// parallel); the dispatch below is compiled in a unit of its own.
+template <int MIXED, int NW>
+hipError_t launch_batched_mn(const BatchArgs& a, int grid, hipStream_t s);
+
+#if defined(RGFK_BMIXED)
 template <int MIXED, int NW>
 __global__ __launch_bounds__(64 * NW, 8 / NW) void rgf_batched_kernel(BatchArgs a) {
   __shared__ GJShared sh;
@@ -392,6 +398,21 @@ __global__ __launch_bounds__(64 * NW, 8 / NW) void rgf_batched_kernel(BatchArgs 
   }
 }
 
+template <>
+hipError_t launch_batched_mn<RGFK_BMIXED, RGFK_BNW>(const BatchArgs& a, int grid, hipStream_t s) {
+  hipLaunchKernelGGL((rgf_batched_kernel<RGFK_BMIXED, RGFK_BNW>), dim3(grid), dim3(64 * RGFK_BNW), 0, s, a);
+  return hipGetLastError();
+}
+#else
+template <>
+hipError_t launch_batched_mn<0, 4>(const BatchArgs& a, int grid, hipStream_t s);
+template <>
+hipError_t launch_batched_mn<1, 4>(const BatchArgs& a, int grid, hipStream_t s);
+template <>
+hipError_t launch_batched_mn<0, 8>(const BatchArgs& a, int grid, hipStream_t s);
+template <>
+hipError_t launch_batched_mn<1, 8>(const BatchArgs& a, int grid, hipStream_t s);
+
 __global__ void reset_counter_kernel(int* counter) {
   if (threadIdx.x == 0 && blockIdx.x == 0) counter[0] = 0;
 }
@@ -400,19 +421,10 @@ hipError_t launch_rgf_batched(const BatchArgs& a, int grid, int waves, hipStream
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, s, a.counter);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
-  if (waves == 4) {
-    if (a.mixed)
-      hipLaunchKernelGGL((rgf_batched_kernel<1, 4>), dim3(grid), dim3(256), 0, s, a);
-    else
-      hipLaunchKernelGGL((rgf_batched_kernel<0, 4>), dim3(grid), dim3(256), 0, s, a);
-  } else {
-    if (a.mixed)
-      hipLaunchKernelGGL((rgf_batched_kernel<1, 8>), dim3(grid), dim3(512), 0, s, a);
-    else
-      hipLaunchKernelGGL((rgf_batched_kernel<0, 8>), dim3(grid), dim3(512), 0, s, a);
-  }
-  return hipGetLastError();
+  if (waves == 4) return a.mixed ? launch_batched_mn<1, 4>(a, grid, s) : launch_batched_mn<0, 4>(a, grid, s);
+  return a.mixed ? launch_batched_mn<1, 8>(a, grid, s) : launch_batched_mn<0, 8>(a, grid, s);
 }
+#endif  // RGFK_BMIXED
 #endif  // RGFK_BATCHED_TU
 
 }  // namespace rgfk
