@@ -37,11 +37,11 @@ TRAFFIC_SOURCES = ("paper_2605_19910_amd/csrc/block_engine.h", "paper_2605_19910
                    "paper_2605_19910_amd/csrc/split_engine.h", "paper_2605_19910_amd/csrc/rgf_split.hip")
 MEASURED_TRAFFIC = {
     # sequential sweep with 4 workgroups per energy, l=256, b=128, 64 energies: FETCH_SIZE
-    # 2.77269e+07 KiB x 2.00 + WRITE_SIZE 3.40461e+07 KiB x 1.00 (copy calibration: a 1 GiB copy
+    # 2.95396e+07 KiB x 2.00 + WRITE_SIZE 3.39963e+07 KiB x 1.00 (copy calibration: a 1 GiB copy
     # reads 5.2431e+05 and writes 1.0486e+06 KiB); profiles/rgf_split_kernel_b128_l256_e64_counters.txt
     ("rgf_split_kernel", "c2/rgf_fp64"): {
-        "sha256": "5711b1c0fdbbd74f513e2e16babffea83c6ed0410a7e481ff1c91554b763d911",
-        "bytes": 9.164560e+10},
+        "sha256": "db71dcab1bab774cdffaa00e7603c207811881ba2bcb33468ae12229de328e7e",
+        "bytes": 9.530703e+10},
 }
 
 
@@ -599,8 +599,11 @@ def bench_ndiag(args):
 
         res, times = _timed_steps(args, step, plan, stream, ne, leg)
         res["all_info_zero"] = bool((info == 0).all())
+        if leg.startswith("nrgf"):
+            res["workgroups_per_energy"] = plan.split_workgroups()
         Ts[leg] = T.clone()
         flops_of = {"nrgf_sweep_kernel": nrgf_flops_per_energy(l, b, w) * ne,
+                    "nrgf_split_kernel": nrgf_flops_per_energy(l, b, w) * ne,
                     # DDRGF runs on the w-layer super-block form (l/w layers of w b)
                     "ddrgf_interior_kernel": ddrgf_interior_flops(l // w, w * b, m, ne,
                                                                   is_hermitian_band(Hf_np) and wl.eta_d == 0.0),
