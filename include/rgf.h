@@ -115,8 +115,14 @@ typedef struct {
                                 products (0 = 1e-5, the mixed-precision error target) */
   int64_t inner_domains;     /* DDRGF, FP64: 0 = the reduced separator system is solved by the
                                 sequential sweep; m2 >= 1 = by DDRGF with m2 pairs (two-level
-                                recursion of Algorithm 2's step 3); needs num_domains >= 2 m2
-                                (counted in w-layer groups for w > 1) */
+                                recursion of Algorithm 2's step 3); needs num_domains >= 2 m2;
+                                w = 1, or w > 1 in the super-block form */
+  int64_t ddrgf_form;        /* DDRGF with w > 1: 0 = native n-diagonal interiors (Sec. 2.3 RGF
+                                inside each interior, w first and last block rows and columns as
+                                halos, reduced system on the m w separator layers as a band of
+                                half bandwidth 2w - 1); 1 = w-layer super-block form (w layers
+                                become one layer of w b orbitals, then the tridiagonal kernels;
+                                needs l % w == 0 and w b <= 128).  Must be 0 otherwise. */
 } rgf_desc_t;
 
 /* Validate a description and build a plan.  *workspace_bytes receives the size of
@@ -195,7 +201,10 @@ rgf_status_t rgf_plan_split_workgroups(rgf_plan_t plan, int32_t* workgroups_per_
 /* DDRGF (Algorithm 2, one level): interiors of every energy are eliminated
  * independently, separators are stitched through the reduced block-tridiagonal
  * Schur complement (Proposition 4), solved by Algorithm 1, and the band of G is
- * recovered (Algorithm 2, steps 4-5).  Same arguments as rgf_solve; the plan must
+ * recovered (Algorithm 2, steps 4-5).  For w > 1 (separators of w layers) the
+ * interiors run the n-diagonal RGF of Sec. 2.3 and the reduced system is solved
+ * by it too (desc ddrgf_form = 0), or everything runs on w-layer super-blocks
+ * (ddrgf_form = 1).  Same arguments as rgf_solve; the plan must
  * have been created with method = RGF_METHOD_DDRGF (else RGF_ERR_PLAN_MISMATCH). */
 rgf_status_t ddrgf_solve(rgf_plan_t plan, const void* H, const void* sigma_L, const void* sigma_R,
                          const double* energies, double eta_d, void* G, double* T, int32_t* info,

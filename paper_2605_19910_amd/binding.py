@@ -24,6 +24,7 @@ STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported configuration", 3: "ou
           6: "plan does not match the entry point"}
 PRECISION = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 METHOD = {"rgf": 0, "sequential": 0, "ddrgf": 1}
+DDRGF_FORM = {"native": 0, "fused": 1}
 
 
 class RgfDesc(ctypes.Structure):
@@ -41,6 +42,7 @@ class RgfDesc(ctypes.Structure):
         ("checkpoint_domains", ctypes.c_int64),
         ("mixed_tolerance", ctypes.c_double),
         ("inner_domains", ctypes.c_int64),
+        ("ddrgf_form", ctypes.c_int64),
     ]
 
 
@@ -135,12 +137,13 @@ class Plan:
     def __init__(self, l: int, b: int, w: int, ne: int, method: str = "rgf", precision: str = "fp64",
                  domains: int = 0, separator_layers: int = 0, want_transmission: bool = True,
                  want_backward: bool = False, checkpoint_domains: int = 0, mixed_tolerance: float = 0.0,
-                 inner_domains: int = 0):
+                 inner_domains: int = 0, ddrgf_form: str = "native"):
         self.lib = load()
         wb = int(want_backward) if not isinstance(want_backward, bool) else (BACKWARD_ONSITE if want_backward else 0)
         self.desc = RgfDesc(l, b, w, ne, PRECISION[precision], METHOD[method], domains,
                             separator_layers, 1 if want_transmission else 0, wb,
-                            checkpoint_domains, float(mixed_tolerance), int(inner_domains))
+                            checkpoint_domains, float(mixed_tolerance), int(inner_domains),
+                            DDRGF_FORM[ddrgf_form])
         self.handle = _VP()
         ws = ctypes.c_size_t(0)
         st = self.lib.rgf_plan_create(ctypes.byref(self.desc), ctypes.byref(self.handle), ctypes.byref(ws))
@@ -304,11 +307,12 @@ def ddrgf_solve(plan: Plan, H, sigma_L, sigma_R, energies, eta_d: float, G, T, i
 
 def solve(H, sigma_L, sigma_R, energies, eta_d: float = 0.0, method: str = "rgf",
           precision: str = "fp64", domains: int = 0, want_transmission: bool = True,
-          plan: Optional[Plan] = None, workspace=None, out=None) -> Tuple:
+          plan: Optional[Plan] = None, workspace=None, out=None, ddrgf_form: str = "native") -> Tuple:
     """Allocate outputs (torch, on H's device) and run one solve on the current stream.
     method "auto" times the sequential sweep and DDRGF with each admissible domain
     count on these inputs once per workload signature and uses the fastest
-    (paper_2605_19910_amd.dispatch).
+    (paper_2605_19910_amd.dispatch).  ddrgf_form: "native" (n-diagonal interiors) or
+    "fused" (w-layer super-blocks), for DDRGF with w > 1.
 
     H: complex128 [2w+1, l, b, b]; sigma_L, sigma_R: complex128 [nE, b, b];
     energies: float64 [nE].  Returns (G [nE, 2w+1, l, b, b], T [nE], info [nE])."""
@@ -331,7 +335,8 @@ def solve(H, sigma_L, sigma_R, energies, eta_d: float = 0.0, method: str = "rgf"
         else:
             inner = 0
         plan = Plan(l, b, w, ne, method=method, precision=precision, domains=domains,
-                    want_transmission=want_transmission, inner_domains=inner)
+                    want_transmission=want_transmission, inner_domains=inner,
+                    ddrgf_form=ddrgf_form if (method == "ddrgf" and w > 1) else "native")
     dev = H.device
     if out is None:
         G = torch.empty((ne, nb, l, b, b), dtype=torch.complex128, device=dev)

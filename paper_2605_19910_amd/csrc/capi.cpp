@@ -33,7 +33,14 @@ struct rgf_plan_s {
   size_t dd2_int_chain = 0, dd2_red_chain = 0;
   size_t off2_int = 0, off2_ms = 0, off2_gs = 0, off2_gsrow = 0, off2_red = 0, off2_fin = 0, off2_info = 0,
          off2_band = 0;
-  // w > 1 DDRGF: super-block copies of the inputs and of the output band
+  // w > 1 DDRGF, native form: per (energy, interior) chains, reduced band (half bandwidth
+  // 2w - 1 over the m w separator layers) and its inverse, the inverse's first w rows at
+  // the last column, the reduced sweep's workspace, finalize scratch, status
+  int ndd = 0;
+  size_t nd_int_chain = 0, nd_red_chain = 0;
+  size_t offn_int = 0, offn_ms = 0, offn_gs = 0, offn_gslast = 0, offn_red = 0, offn_fin = 0, offn_info = 0,
+         offn_infored = 0;
+  // w > 1 DDRGF, super-block form: copies of the inputs and of the output band
   int fl, fb;                    // super-layers and super-block size of the DDRGF system
   size_t off_hf, off_slf, off_srf, off_gf, off_inff;
   // batched plans
@@ -135,12 +142,17 @@ rgf_status_t validate(const rgf_desc_t* d) {
     if (s1 != w) return RGF_ERR_UNSUPPORTED;
     if (d->num_domains < 1) return RGF_ERR_INVALID_ARG;
     if (d->num_layers - d->num_domains * s1 < d->num_domains * w) return RGF_ERR_INVALID_ARG;
-    if (w > 1) {
+    if (d->ddrgf_form != 0 && d->ddrgf_form != 1) return RGF_ERR_INVALID_ARG;
+    if (w == 1 && d->ddrgf_form != 0) return RGF_ERR_INVALID_ARG;
+    if (w > 1 && d->ddrgf_form == 0 && d->inner_domains != 0) return RGF_ERR_UNSUPPORTED;
+    if (w > 1 && d->ddrgf_form == 1) {
       // separators of w layers: the w-layer super-block system must fit the kernels
       if (d->num_layers % w != 0 || w * d->block_size > 128) return RGF_ERR_UNSUPPORTED;
       const int64_t lf = d->num_layers / w;
       if (lf - d->num_domains < d->num_domains) return RGF_ERR_INVALID_ARG;
     }
+  } else if (d->ddrgf_form != 0) {
+    return RGF_ERR_INVALID_ARG;
   }
   return RGF_OK;
 }
@@ -209,7 +221,27 @@ rgf_status_t rgf_plan_create(const rgf_desc_t* desc, rgf_plan_t* plan, size_t* w
     if (desc->want_backward & RGF_BACKWARD_BAND) adj_end += (size_t)p->nch * 3 * l * (size_t)b * b * sizeof(double2);
     p->ws_bytes = align256(std::max(p->off_fwd + fwd, adj_end));
   }
-  if (desc->method == RGF_METHOD_DDRGF) {
+  if (desc->method == RGF_METHOD_DDRGF && w > 1 && desc->ddrgf_form == 0) {
+    const int l = (int)desc->num_layers, m = (int)desc->num_domains, ne = (int)desc->num_energies;
+    const int lr = m * w, wr = 2 * w - 1;
+    const size_t b = (size_t)desc->block_size, bb = b * b, bpbp = (size_t)p->bp * p->bp;
+    int base = 0, rem = 0;
+    rgfk::nddrgf_layout_host(l, m, w, &base, &rem);
+    p->ndd = 1;
+    p->nd_int_chain = rgfk::nddrgf_interior_ws_elems(base + 1, w, p->bp);
+    p->nd_red_chain = rgfk::nrgf_ws_chain_elems(lr, wr, p->bp, w);
+    const size_t red_band = (size_t)(2 * wr + 1) * lr * bb * sizeof(double2) * ne;
+    size_t off = 0;
+    p->offn_int = off;     off = align256(off + p->nd_int_chain * sizeof(double2) * (size_t)ne * m);
+    p->offn_ms = off;      off = align256(off + red_band);
+    p->offn_gs = off;      off = align256(off + red_band);
+    p->offn_gslast = off;  off = align256(off + (size_t)ne * w * bb * sizeof(double2));
+    p->offn_red = off;     off = align256(off + p->nd_red_chain * sizeof(double2) * (size_t)ne);
+    p->offn_fin = off;     off = align256(off + (size_t)ne * 4 * bpbp * sizeof(double2));
+    p->offn_info = off;    off = align256(off + (size_t)ne * m * sizeof(int));
+    p->offn_infored = off; off = align256(off + (size_t)ne * sizeof(int));
+    p->ws_bytes = off;
+  } else if (desc->method == RGF_METHOD_DDRGF) {
     const int l = (int)desc->num_layers / w, m = (int)desc->num_domains, ne = (int)desc->num_energies;
     const size_t b = (size_t)desc->block_size * w, bb = b * b;
     p->fl = l;
@@ -536,6 +568,50 @@ rgf_status_t ddrgf_solve(rgf_plan_t plan, const void* H, const void* sigma_L, co
   hipStream_t st = static_cast<hipStream_t>(stream);
   TimedScope timed(plan, st);
   const int w = (int)d.half_bandwidth;
+  if (plan->ndd) {
+    // native n-diagonal DDRGF (separators of w layers)
+    const int m = (int)d.num_domains, lr = m * w, wr = 2 * w - 1;
+    const size_t bb = (size_t)d.block_size * d.block_size;
+    rgfk::NDDArgs a{};
+    a.H = static_cast<const double2*>(H);
+    a.sigL = static_cast<const double2*>(sigma_L);
+    a.sigR = static_cast<const double2*>(sigma_R);
+    a.E = energies;
+    a.eta_d = eta_d;
+    a.G = static_cast<double2*>(G);
+    a.T = d.want_transmission ? T : nullptr;
+    a.info = info;
+    a.l = (int)d.num_layers;
+    a.b = (int)d.block_size;
+    a.w = w;
+    a.m = m;
+    a.ne = (int)d.num_energies;
+    a.ws_int = reinterpret_cast<double2*>(ws + plan->offn_int);
+    a.ws_int_chain = plan->nd_int_chain;
+    a.MS = reinterpret_cast<double2*>(ws + plan->offn_ms);
+    a.GS = reinterpret_cast<double2*>(ws + plan->offn_gs);
+    a.GSlast = reinterpret_cast<double2*>(ws + plan->offn_gslast);
+    a.info_part = reinterpret_cast<int*>(ws + plan->offn_info);
+    a.info_red = reinterpret_cast<int*>(ws + plan->offn_infored);
+    a.ws_fin = reinterpret_cast<double2*>(ws + plan->offn_fin);
+    rgfk::NSweepArgs r{};
+    r.H = a.MS;
+    r.direct = 1;
+    r.h_stride = (size_t)(2 * wr + 1) * lr * bb;
+    r.E = energies;
+    r.G = a.GS;
+    r.T = nullptr;
+    r.info = a.info_red;
+    r.ws = reinterpret_cast<double2*>(ws + plan->offn_red);
+    r.ws_chain = plan->nd_red_chain;
+    r.l = lr;
+    r.b = a.b;
+    r.w = wr;
+    r.ne = a.ne;
+    r.nr = w;
+    r.rows_last = a.GSlast;
+    return rgfk::launch_nddrgf(a, r, st) == hipSuccess ? RGF_OK : RGF_ERR_HIP;
+  }
   rgfk::FuseArgs f{};
   if (w > 1) {
     f.H = static_cast<const double2*>(H);

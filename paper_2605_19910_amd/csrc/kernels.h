@@ -191,14 +191,47 @@ struct NSweepArgs {
   int l, b, w, ne;
   unsigned* sync;            // split sweep: one group counter per energy, 64 bytes apart
   long long spin_limit;      // split sweep: polls before a group barrier gives up
+  // direct mode (the reduced separator system of the n-diagonal DDRGF): H holds the
+  // band of M itself, every block as it is (no E, eta_d, Sigma), one band per energy
+  int direct;
+  size_t h_stride;           // elements between the bands of consecutive energies (direct)
+  int nr;                    // first block rows propagated to the last column (>= 1)
+  double2* rows_last;        // optional out: blocks (t, l-1), t < nr, at rows_last + (e nr + t) b b
 };
 
-size_t nrgf_ws_chain_elems(int l, int w, int bp);
+// nr: first block rows carried to the last column (1 for a plain solve)
+size_t nrgf_ws_chain_elems(int l, int w, int bp, int nr = 1);
 // n-diagonal sweep with K workgroups per energy (nrgf_split.hip), FP64, padded block
 // size 64 or 128; K from split_workgroups_n (as split_workgroups).
 int split_workgroups_n(int b, int ne, int want);
 hipError_t launch_nrgf_split(const NSweepArgs& a, int K, hipStream_t s);
 hipError_t launch_nrgf_sweep(const NSweepArgs& a, hipStream_t s);
+
+// DDRGF for block n-diagonal systems with separators of w layers (nddrgf.hip).
+struct NDDArgs {
+  const double2* H;          // band [2w+1][l][b][b], shared by all energies
+  const double2* sigL;       // [ne][b][b]
+  const double2* sigR;
+  const double* E;           // [ne]
+  double eta_d;
+  double2* G;                // out band [ne][2w+1][l][b][b]
+  double* T;                 // out [ne] or null
+  int* info;                 // out [ne]
+  int l, b, w, m, ne;
+  double2* ws_int;           // per (energy, interior) chain: ws_int_chain elements
+  size_t ws_int_chain;
+  double2* MS;               // reduced band [ne][4w-1][m w][b][b] (half bandwidth 2w-1)
+  double2* GS;               // its inverse band, same layout
+  double2* GSlast;           // blocks (t, m w - 1), t < w, of the reduced inverse [ne][w][b][b]
+  int* info_part;            // [ne][m]: first failing pivot of each interior (global layer + 1)
+  int* info_red;             // [ne]: first failing pivot of the reduced system (reduced layer + 1)
+  double2* ws_fin;           // [ne][4][bp][bp]
+};
+
+size_t nddrgf_interior_ws_elems(int nmax, int w, int bp);
+void nddrgf_layout_host(int l, int m, int w, int* base, int* rem);
+// red: the n-diagonal sweep arguments of the reduced system (direct mode, nr = w)
+hipError_t launch_nddrgf(const NDDArgs& a, const NSweepArgs& red, hipStream_t s);
 
 // Super-block view (w layers -> one layer of w*b orbitals) of a band and its leads.
 struct FuseArgs {

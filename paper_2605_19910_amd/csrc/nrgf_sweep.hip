@@ -9,15 +9,18 @@
 //   G_{a,i} = -sum_{c in C_i} G_{a,c} U_{c,i},  G_{i,a} = -sum_{c in C_i} L_{i,c} G_{c,a}  (a in C_i)
 //   G_ii = g_i - sum_{c in C_i} L_{i,c} G_{c,i}
 // and the first block row R_i = G_{0,i} = -sum_{c in C_i} R_c U_{c,i} feeds T(E).
+// In direct mode (the reduced separator system of the n-diagonal DDRGF) the band of M
+// is given per energy, and the first nr block rows are carried to the last column:
+// G_{t,i} = -sum_c G_{t,c} U_{c,i} for i > t, with G_{t,c} from the band when c <= t.
 #include "block_engine.h"
 #include "kernels.h"
 
 namespace rgfk {
 
 #ifndef RGFK_INST_T
-size_t nrgf_ws_chain_elems(int l, int w, int bp) {
-  // S band (2w+1) l, g l, U w l, L w l, R l, Gamma_L, Gamma_R, X1
-  return ((size_t)(4 * w + 3) * l + 3) * (size_t)bp * bp;
+size_t nrgf_ws_chain_elems(int l, int w, int bp, int nr) {
+  // S band (2w+1) l, g l, U w l, L w l, R l, Gamma_L, Gamma_R, X1, rows 1..nr-1 (l each)
+  return ((size_t)(4 * w + 3) * l + 3 + (size_t)(nr - 1) * l) * (size_t)bp * bp;
 }
 #endif
 
@@ -38,16 +41,19 @@ __global__ __launch_bounds__(64 * NW, 1) void nrgf_sweep_kernel(NSweepArgs a) {
   double2* GamL = R + (size_t)l * bpbp;
   double2* GamR = GamL + bpbp;
   double2* X1 = GamR + bpbp;
-  const double2* sL = a.sigL + (size_t)e * bb;
-  const double2* sR = a.sigR + (size_t)e * bb;
+  double2* Rx = X1 + bpbp;                           // rows t >= 1: G_{t,i} at (t-1) l + i
+  const double2* sL = a.direct ? nullptr : a.sigL + (size_t)e * bb;
+  const double2* sR = a.direct ? nullptr : a.sigR + (size_t)e * bb;
+  const double2* Hband = a.H + (a.direct ? (size_t)e * a.h_stride : 0);
   const double2 z = make_double2(a.E[e], a.eta_d);
   double2* Gout = a.G + (size_t)e * (2 * w + 1) * l * bb;
 
   auto Sblk = [&](int i, int j) { return Sw + ((size_t)(w + j - i) * l + i) * bpbp; };
-  auto Hblk = [&](int i, int j) { return a.H + ((size_t)(w + j - i) * l + i) * bb; };
+  auto Hblk = [&](int i, int j) { return Hband + ((size_t)(w + j - i) * l + i) * bb; };
   auto Gblk = [&](int i, int j) { return Gout + ((size_t)(w + j - i) * l + i) * bb; };
   auto Ublk = [&](int c, int i) { return U + ((size_t)i * w + (i - c - 1)) * bpbp; };
   auto Lblk = [&](int i, int c) { return L + ((size_t)i * w + (i - c - 1)) * bpbp; };
+  auto Rrow = [&](int tr, int i) { return Rx + ((size_t)(tr - 1) * l + i) * bpbp; };
   auto P = [&](const double2* p) { return opnd(p, BP, BP, BP); };
   auto Pb = [&](const double2* p) { return opnd(p, b, b, b); };
 
@@ -59,10 +65,14 @@ __global__ __launch_bounds__(64 * NW, 1) void nrgf_sweep_kernel(NSweepArgs a) {
     for (int k = -w; k <= w; ++k) {
       const int j = i + k;
       if (j < 0 || j >= l) continue;
-      if (k == 0)
+      if (a.direct) {
+        load<T, NW>(acc, Pb(Hblk(i, j)));
+        if (k == 0) add_identity_beyond<T, NW>(acc, b);
+      } else if (k == 0) {
         assemble_diag<T, NW>(acc, Hblk(i, i), b, z, i == 0 ? sL : nullptr, i == l - 1 ? sR : nullptr);
-      else
+      } else {
         load<T, NW>(acc, Pb(Hblk(i, j)), -1.0);
+      }
       store<T, NW>(acc, Sblk(i, j), BP, BP, BP);
     }
   }
@@ -111,6 +121,12 @@ __global__ __launch_bounds__(64 * NW, 1) void nrgf_sweep_kernel(NSweepArgs a) {
     acc_zero<T, NW>(acc);
     for (int c = c0; c < i; ++c) mma<T, NW>(acc, P(R + (size_t)c * bpbp), P(Ublk(c, i)), -1.0);
     store<T, NW>(acc, R + (size_t)i * bpbp, BP, BP, BP);
+    for (int tr = 1; tr < a.nr && tr < i; ++tr) {
+      acc_zero<T, NW>(acc);
+      for (int c = c0; c < i; ++c)
+        mma<T, NW>(acc, c <= tr ? Pb(Gblk(tr, c)) : P(Rrow(tr, c)), P(Ublk(c, i)), -1.0);
+      store<T, NW>(acc, Rrow(tr, i), BP, BP, BP);
+    }
     __syncthreads();
     load<T, NW>(acc, P(g + (size_t)i * bpbp));
     for (int c = c0; c < i; ++c) mma<T, NW>(acc, P(Lblk(i, c)), Pb(Gblk(c, i)), -1.0);
@@ -120,6 +136,16 @@ __global__ __launch_bounds__(64 * NW, 1) void nrgf_sweep_kernel(NSweepArgs a) {
 
   double Tval = 0.0;
   if (a.T) Tval = transmission<T, NW>(acc, R + (size_t)(l - 1) * bpbp, sL, sR, b, GamL, GamR, X1, red);
+  if (a.rows_last) {
+    // blocks (tr, l-1): from the band when tr = l-1, else from the propagated rows
+    for (int tr = 0; tr < a.nr && tr < l; ++tr) {
+      if (tr == l - 1)
+        load<T, NW>(acc, Pb(Gblk(tr, l - 1)));
+      else
+        load<T, NW>(acc, P(tr == 0 ? R + (size_t)(l - 1) * bpbp : Rrow(tr, l - 1)));
+      store<T, NW>(acc, a.rows_last + ((size_t)e * a.nr + tr) * bb, b, b, b);
+    }
+  }
 
   if (bad_layer >= 0) {
     const double qnan = __builtin_nan("");

@@ -33,10 +33,9 @@ def signature(l: int, b: int, w: int, ne: int, precision: str, device: str) -> s
 def candidates(l: int, b: int, w: int, precision: str = "fp64",
                methods: Iterable[str] = ("rgf", "ddrgf")) -> List[Tuple]:
     """Admissible candidates: ("rgf", 0), the sequential sweep; ("ddrgf", m), DDRGF
-    (FP64 only) with separators of w layers and interiors of at least w layers (for
-    w > 1 the w-layer super-blocks must fit the kernels: l divisible by w, w b <= 128);
-    ("ddrgf", m, m2), two-level DDRGF with m2 inner pairs, for m >= 16 and
-    m2 in {2, 4, 8} with m >= 2 m2."""
+    (FP64 only) with separators of w layers and interiors of at least w layers (native
+    n-diagonal interiors for w > 1); ("ddrgf", m, m2), two-level DDRGF with m2 inner
+    pairs, for w = 1, m >= 16 and m2 in {2, 4, 8} with m >= 2 m2."""
     out: List[Tuple] = []
     if "rgf" in methods:
         out.append(("rgf", 0))
@@ -44,10 +43,8 @@ def candidates(l: int, b: int, w: int, precision: str = "fp64",
         for m in DOMAIN_CANDIDATES:
             if l - m * w < m * w:
                 continue
-            if w > 1 and (l % w != 0 or w * b > 128 or l // w - m < m):
-                continue
             out.append(("ddrgf", m))
-            if m >= 16:
+            if m >= 16 and w == 1:
                 out += [("ddrgf", m, m2) for m2 in (2, 4, 8) if m >= 2 * m2]
     return out
 

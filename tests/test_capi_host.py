@@ -71,8 +71,12 @@ def test_plan_workspace_size(l, b, w, ne):
     (dict(l=4, b=4, w=1, ne=1, precision="bf16x3"), 2),
     (dict(l=8, b=4, w=2, ne=1, precision="fp32"), 2),
     (dict(l=8, b=4, w=1, ne=1, method="ddrgf", domains=2, precision="fp32"), 2),
-    (dict(l=9, b=4, w=2, ne=1, method="ddrgf", domains=2), 2),
-    (dict(l=8, b=80, w=2, ne=1, method="ddrgf", domains=2), 2),
+    (dict(l=9, b=4, w=2, ne=1, method="ddrgf", domains=2, ddrgf_form="fused"), 2),
+    (dict(l=8, b=80, w=2, ne=1, method="ddrgf", domains=2, ddrgf_form="fused"), 2),
+    (dict(l=7, b=4, w=2, ne=1, method="ddrgf", domains=2), 1),
+    (dict(l=32, b=4, w=2, ne=1, method="ddrgf", domains=4, inner_domains=2), 2),
+    (dict(l=8, b=4, w=1, ne=1, method="ddrgf", domains=2, ddrgf_form="fused"), 1),
+    (dict(l=8, b=4, w=2, ne=1, ddrgf_form="fused"), 1),
     (dict(l=8, b=4, w=1, ne=1, method="ddrgf", domains=5), 1),
     (dict(l=8, b=4, w=1, ne=1, method="ddrgf", domains=2, want_backward=True), 2),
     (dict(l=8, b=4, w=1, ne=1, precision="fp32", want_backward=True), 2),
@@ -204,4 +208,25 @@ def test_timing_argument_errors():
     assert lib.rgf_plan_set_timing(p.handle, 0, 0) == 0     # disabling is always fine
     with pytest.raises(binding.RgfError):
         p.kernel_times()
+    p.close()
+
+
+@pytest.mark.parametrize("l,b,w,m,ne", [(9, 4, 2, 2, 3), (40, 64, 2, 8, 2), (26, 100, 3, 3, 1), (33, 128, 4, 2, 2)])
+def test_native_ndiagonal_ddrgf_workspace(l, b, w, m, ne):
+    """Native n-diagonal DDRGF plans (no l % w or w b <= 128 condition): interiors of
+    (2w^2 + 8w + 2) nmax + 2w blocks each, reduced band and inverse (half bandwidth
+    2w - 1 over m w layers), w last-column rows, the reduced sweep, scratch, status."""
+    binding = _lib()
+    p = binding.Plan(l, b, w, ne, method="ddrgf", domains=m)
+    bp = (b + 15) // 16 * 16
+    B = bp * bp * 16
+    al = lambda x: (x + 255) // 256 * 256
+    nmax = (l - m * w) // m + 1
+    lr, wr = m * w, 2 * w - 1
+    chain = ((2 * w * w + 8 * w + 2) * nmax + 2 * w) * B
+    red_chain = ((4 * wr + 3) * lr + 3 + (w - 1) * lr) * B
+    band = (2 * wr + 1) * lr * b * b * 16 * ne
+    want = (al(chain * ne * m) + 2 * al(band) + al(ne * w * b * b * 16) + al(red_chain * ne)
+            + al(ne * 4 * B) + al(ne * m * 4) + al(ne * 4))
+    assert p.workspace_bytes == want
     p.close()

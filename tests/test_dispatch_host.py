@@ -10,11 +10,11 @@ def test_candidates():
     assert c[0] == ("rgf", 0)
     assert [x[1] for x in c if x[0] == "ddrgf" and len(x) == 2] == [2, 4, 8, 16, 32]
     assert [x[1:] for x in c if len(x) == 3] == [(16, 2), (16, 4), (16, 8), (32, 2), (32, 4), (32, 8)]
-    # w = 2: super-blocks of w b must fit 128, l divisible by w, interiors >= w layers
-    assert [x[1] for x in dispatch.candidates(512, 64, 2, "fp64") if len(x) == 2 and x[0] == "ddrgf"] == \
-        [2, 4, 8, 16, 32]
-    assert dispatch.candidates(512, 100, 2, "fp64") == [("rgf", 0)]
-    assert dispatch.candidates(511, 64, 2, "fp64") == [("rgf", 0)]
+    # w = 2: native n-diagonal DDRGF, interiors of at least w layers, one level only
+    assert [x for x in dispatch.candidates(512, 64, 2, "fp64") if x[0] == "ddrgf"] == \
+        [("ddrgf", m) for m in (2, 4, 8, 16, 32)]
+    assert [x[1] for x in dispatch.candidates(511, 100, 2, "fp64") if x[0] == "ddrgf"] == [2, 4, 8, 16, 32]
+    assert [x[1] for x in dispatch.candidates(30, 64, 3, "fp64") if x[0] == "ddrgf"] == [2, 4]
     assert [x[1] for x in dispatch.candidates(10, 8, 1, "fp64") if x[0] == "ddrgf"] == [2, 4]
     # mixed precision: sequential only; methods filter
     assert dispatch.candidates(256, 128, 1, "fp32") == [("rgf", 0)]

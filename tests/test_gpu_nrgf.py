@@ -30,14 +30,31 @@ def test_native_ndiagonal(lib, l, b, w):
     check_fp64(f"nrgf l={l} b={b} w={w}", G, T, range(2), oracle_results("nrgf", wl, range(2)), w, b)
 
 
+@pytest.mark.parametrize("form", ["native", "fused"])
 @pytest.mark.parametrize("l,b,w,m", [(8, 8, 2, 2), (20, 16, 2, 4), (24, 20, 2, 5), (18, 12, 3, 2),
                                      (40, 64, 2, 8), (12, 32, 2, 3)])
-def test_ddrgf_ndiagonal(lib, l, b, w, m):
+def test_ddrgf_ndiagonal(lib, l, b, w, m, form):
+    """Both forms of DDRGF with separators of w layers against the oracle's DDRGF (same
+    interior layout where l - m w splits into multiples of w) and the dense inverse."""
     wl = make_random(l, b, w, 2, seed=1700 + l + b + w + m, eta=1e-3)
+    G, T, info = run_gpu(lib, wl, method="ddrgf", domains=m, ddrgf_form=form)
+    assert np.all(info == 0)
+    refs = oracle_results("ddrgf", wl, range(2), m=m)
+    check_dd(f"ddrgf/{form} l={l} b={b} w={w} m={m}", G, T, range(2), refs, oracle_results("dense", wl, range(2)), w)
+
+
+@pytest.mark.parametrize("l,b,w,m", [(16, 100, 2, 3), (21, 128, 2, 2), (26, 40, 4, 3), (17, 7, 3, 2),
+                                     (9, 16, 2, 2), (45, 33, 2, 7)])
+def test_ddrgf_ndiagonal_native_only(lib, l, b, w, m):
+    """Native n-diagonal DDRGF where the super-block form cannot run (w b > 128 or l
+    not a multiple of w), with ragged interiors, against the oracle's DDRGF (same
+    layout) and the dense inverse."""
+    wl = make_random(l, b, w, 2, seed=1900 + l + b + w + m, eta=1e-3)
     G, T, info = run_gpu(lib, wl, method="ddrgf", domains=m)
     assert np.all(info == 0)
     refs = oracle_results("ddrgf", wl, range(2), m=m)
-    check_dd(f"ddrgf l={l} b={b} w={w} m={m}", G, T, range(2), refs, oracle_results("dense", wl, range(2)), w)
+    check_dd(f"ddrgf/native l={l} b={b} w={w} m={m}", G, T, range(2), refs,
+             oracle_results("dense", wl, range(2)), w)
 
 
 def test_config3_sequential(lib):

@@ -26,19 +26,19 @@ def to_dev(wl):
             torch.from_numpy(wl.sigma_R).to(d), torch.from_numpy(wl.energies).to(d))
 
 
-def run_gpu_dev(lib, wl, method="rgf", eta_d=None, domains=0, precision="fp64"):
+def run_gpu_dev(lib, wl, method="rgf", eta_d=None, domains=0, precision="fp64", ddrgf_form="native"):
     """Solve on the GPU; returns (G, T, info) as device tensors."""
     import torch
     H, sL, sR, E = to_dev(wl)
     G, T, info = lib.solve(H, sL, sR, E, eta_d=wl.eta_d if eta_d is None else eta_d, method=method,
-                           domains=domains, precision=precision)
+                           domains=domains, precision=precision, ddrgf_form=ddrgf_form)
     torch.cuda.synchronize()
     return G, T, info
 
 
-def run_gpu(lib, wl, method="rgf", eta_d=None, domains=0, precision="fp64"):
+def run_gpu(lib, wl, method="rgf", eta_d=None, domains=0, precision="fp64", ddrgf_form="native"):
     """Solve on the GPU; returns host arrays (small systems only)."""
-    G, T, info = run_gpu_dev(lib, wl, method, eta_d, domains, precision)
+    G, T, info = run_gpu_dev(lib, wl, method, eta_d, domains, precision, ddrgf_form)
     return G.cpu().numpy(), T.cpu().numpy(), info.cpu().numpy()
 
 
