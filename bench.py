@@ -111,11 +111,17 @@ def fused_band(H, w: int):
 
 
 def is_hermitian_band(H) -> bool:
-    """H (band [3, l, b, b]) exactly Hermitian, as the library's device check decides."""
+    """H (band [2w+1, l, b, b], block (i, i+d-w) at [d, i]) exactly Hermitian, as the
+    library's device check decides."""
     import numpy as np
-    d = np.array_equal(H[1], np.conj(np.swapaxes(H[1], 1, 2)))
-    o = np.array_equal(H[0][1:], np.conj(np.swapaxes(H[2][:-1], 1, 2)))
-    return bool(d and o)
+    w = (H.shape[0] - 1) // 2
+    for d in range(w + 1):
+        k = w - d                      # block (i, i-k) against block (i-k, i)
+        lo = H[d][k:]
+        up = H[2 * w - d][:H.shape[1] - k]
+        if not np.array_equal(lo, np.conj(np.swapaxes(up, 1, 2))):
+            return False
+    return True
 
 
 def ddrgf_recover_flops(l: int, b: int, m: int, ne: int) -> float:
@@ -130,6 +136,55 @@ def ddrgf_recover_flops(l: int, b: int, m: int, ne: int) -> float:
         left = k > 0
         tot += n * (4 if left else 1) + (3 * n - 2) * (2 if left else 1) + (4 if left else 1)
     return tot * 8.0 * float(b) ** 3 * ne
+
+
+def nddrgf_interior_flops(l: int, b: int, w: int, m: int, ne: int, hermitian: bool = False) -> float:
+    """Flops executed by the native n-diagonal DDRGF interior kernel, 8 b^3 per complex
+    product or Gauss-Jordan inversion, counted per interior of n layers as the kernel
+    runs them: upward step i (c = min(w, i) coupled layers): 1 inversion, 2c multipliers,
+    c^2 Schur products, 2 w c transfer products; downward step i >= 1: 2c^2 + c band
+    products; last-column/row halos 2 w min(w, i + 1) per layer; with a left separator
+    the first w rows/columns w^2 (w + 1) once and 2 w^2 per layer from layer w on.
+    With ``hermitian`` (H Hermitian, eta_d = 0) the interiors without a lead skip the
+    row transfer products (Q = P^H): w c fewer per upward step."""
+    base, rem = divmod(l - m * w, m)
+    ops = 0
+    for k in range(m):
+        n = base + (1 if k < rem else 0)
+        herm = hermitian and k > 0
+        for i in range(n):
+            c = min(w, i)
+            if herm:
+                ops += 1 + 2 * c + c * c + w * c               # upward, Hermitian
+            else:
+                ops += 1 + 2 * c + c * c + 2 * w * c           # upward
+            if i >= 1:
+                ops += 2 * c * c + c                          # band of X
+            ops += 2 * w * min(w, i + 1)                      # CR, RR
+            if k > 0 and i >= w:
+                ops += 2 * w * w                              # CL, RL recursions
+        if k > 0:
+            ops += w * w * (w + 1)                            # CL, RL of the first w layers
+    return 8.0 * float(b) ** 3 * ops * ne
+
+
+def nddrgf_recover_flops(l: int, b: int, w: int, m: int, ne: int) -> float:
+    """Flops executed by the native n-diagonal DDRGF recovery kernel, 8 b^3 per
+    product: per interior layer (g = 2 separator groups, 1 for the first interior)
+    (g w)^2 for V_i and g w per band block of the interior row, plus g w per
+    separator-row block next to the interior and w^2 (no products) for the
+    separator's own blocks."""
+    base, rem = divmod(l - m * w, m)
+    ops = 0
+    for k in range(m):
+        n = base + (1 if k < rem else 0)
+        g = 2 if k > 0 else 1
+        a = k * (base + w) + min(k, rem)
+        seps = ([a - w + s for s in range(w)] if k > 0 else []) + [a + n + s for s in range(w)]
+        for i in range(n):
+            ops += (g * w) ** 2 + g * w * (min(n - 1, i + w) - max(0, i - w) + 1)
+            ops += g * w * sum(1 for q in seps if abs(q - (a + i)) <= w)
+    return 8.0 * float(b) ** 3 * ops * ne
 
 
 def nrgf_flops_per_energy(l: int, b: int, w: int) -> float:
@@ -584,12 +639,13 @@ def bench_ndiag(args):
     info = torch.empty((ne,), dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream(dev)
     legs, rooflines, Ts = {}, {}, {}
-    for leg in ("nrgf_fp64", "ddrgf_fp64"):
+    for leg in ("nrgf_fp64", "ddrgf_fp64", "ddrgf_fused_fp64"):
         if leg.startswith("nrgf"):
             plan = binding.Plan(l, b, w, ne, method="rgf")
             fn = binding.rgf_solve
         else:
-            plan = binding.Plan(l, b, w, ne, method="ddrgf", domains=m)
+            plan = binding.Plan(l, b, w, ne, method="ddrgf", domains=m,
+                                ddrgf_form="fused" if "fused" in leg else "native")
             fn = binding.ddrgf_solve
         ws = torch.empty((plan.workspace_bytes,), dtype=torch.uint8, device=dev)
         log(f"{leg}: workspace {plan.workspace_bytes / 2**30:.1f} GiB")
@@ -607,12 +663,16 @@ def bench_ndiag(args):
                     # DDRGF runs on the w-layer super-block form (l/w layers of w b)
                     "ddrgf_interior_kernel": ddrgf_interior_flops(l // w, w * b, m, ne,
                                                                   is_hermitian_band(Hf_np) and wl.eta_d == 0.0),
-                    "ddrgf_recover_kernel": ddrgf_recover_flops(l // w, w * b, m, ne)}
+                    "ddrgf_recover_kernel": ddrgf_recover_flops(l // w, w * b, m, ne),
+                    "nddrgf_interior_kernel": nddrgf_interior_flops(l, b, w, m, ne,
+                                                                    is_hermitian_band(wl.H) and wl.eta_d == 0.0),
+                    "nddrgf_recover_kernel": nddrgf_recover_flops(l, b, w, m, ne)}
         rooflines[leg] = _roofline(times, flops_of, leg)
         legs[leg] = res
         del ws, plan
         torch.cuda.empty_cache()
-    dT = ((Ts["ddrgf_fp64"] - Ts["nrgf_fp64"]).abs() / torch.clamp(Ts["nrgf_fp64"].abs(), min=1.0)).max().item()
+    dT = {leg: ((Ts[leg] - Ts["nrgf_fp64"]).abs() / torch.clamp(Ts["nrgf_fp64"].abs(), min=1.0)).max().item()
+          for leg in ("ddrgf_fp64", "ddrgf_fused_fp64")}
     best = max(legs, key=lambda k: legs[k]["value"])
     out = {
         "metric": "energy points/sec (selected G^R + T(E))", "value": round(legs[best]["value"], 3),
@@ -623,7 +683,8 @@ def bench_ndiag(args):
         "config": {"workload": f"block pentadiagonal (w=2, next-nearest blocks x0.3), l={l}, b={b}, "
                                f"{ne} energies in [-2,2], eta=1e-4, seed 103",
                    "method": {"nrgf_fp64": "native block n-diagonal sweep",
-                              "ddrgf_fp64": f"DDRGF, {m} domains, separators of w layers"}[best]},
+                              "ddrgf_fp64": f"DDRGF, {m} domains, separators of w layers, n-diagonal interiors",
+                              "ddrgf_fused_fp64": f"DDRGF, {m} domains, on w-layer super-blocks"}[best]},
         "roofline": rooflines[best],
         "legs": legs, "rooflines": rooflines, "T_rel_diff_ddrgf_vs_sequential": dT,
     }

@@ -39,7 +39,7 @@ struct rgf_plan_s {
   int ndd = 0;
   size_t nd_int_chain = 0, nd_red_chain = 0;
   size_t offn_int = 0, offn_ms = 0, offn_gs = 0, offn_gslast = 0, offn_red = 0, offn_fin = 0, offn_info = 0,
-         offn_infored = 0;
+         offn_infored = 0, offn_herm = 0;
   // w > 1 DDRGF, super-block form: copies of the inputs and of the output band
   int fl, fb;                    // super-layers and super-block size of the DDRGF system
   size_t off_hf, off_slf, off_srf, off_gf, off_inff;
@@ -240,6 +240,7 @@ rgf_status_t rgf_plan_create(const rgf_desc_t* desc, rgf_plan_t* plan, size_t* w
     p->offn_fin = off;     off = align256(off + (size_t)ne * 4 * bpbp * sizeof(double2));
     p->offn_info = off;    off = align256(off + (size_t)ne * m * sizeof(int));
     p->offn_infored = off; off = align256(off + (size_t)ne * sizeof(int));
+    p->offn_herm = off;    off = align256(off + sizeof(int));
     p->ws_bytes = off;
   } else if (desc->method == RGF_METHOD_DDRGF) {
     const int l = (int)desc->num_layers / w, m = (int)desc->num_domains, ne = (int)desc->num_energies;
@@ -594,6 +595,7 @@ rgf_status_t ddrgf_solve(rgf_plan_t plan, const void* H, const void* sigma_L, co
     a.info_part = reinterpret_cast<int*>(ws + plan->offn_info);
     a.info_red = reinterpret_cast<int*>(ws + plan->offn_infored);
     a.ws_fin = reinterpret_cast<double2*>(ws + plan->offn_fin);
+    a.herm = reinterpret_cast<int*>(ws + plan->offn_herm);
     rgfk::NSweepArgs r{};
     r.H = a.MS;
     r.direct = 1;

@@ -226,6 +226,7 @@ struct NDDArgs {
   int* info_part;            // [ne][m]: first failing pivot of each interior (global layer + 1)
   int* info_red;             // [ne]: first failing pivot of the reduced system (reduced layer + 1)
   double2* ws_fin;           // [ne][4][bp][bp]
+  int* herm;                 // device flag: H exactly Hermitian (set by the check kernel), or null
 };
 
 size_t nddrgf_interior_ws_elems(int nmax, int w, int bp);

@@ -24,6 +24,15 @@
 //      separator] and P_{i-1}[t] = P_i[t-1] - U_{i-w+t,i} P_i[w-1] (P_i[-1] = 0), formed
 //      in the upward pass; the rows mirror it: RR_j = Q_j sigma_j with
 //      Q_{i-1}[.][t] = Q_i[.][t-1] - Q_i[.][w-1] L_{i,i-w+t}.
+//      Hermitian interiors (H exactly Hermitian, checked on the device, eta_d = 0, no
+//      lead in the interior): the transfer products of the rows are those of the
+//      columns conjugated, Q_i = P_i^H, and are not formed.  The other Hermitian
+//      identities (U_{c,i} = L_{i,c}^H, a Schur window updated in its lower triangle
+//      only, the upper band or the row halos as conjugate transposes) are exact too,
+//      but for w >= 2 they tie rounding errors of the two triangles together: on
+//      interiors of tens of layers the lower-triangle Schur update alone diverges
+//      (relative band error 1e-2 .. 1e-1 at 100 layers of 4 orbitals), and U = L^H or
+//      conjugated halos cost one to two digits, so they are not used.
 //   2. nddrgf_schur_kernel  one workgroup per (energy, separator): the reduced system
 //      T_S = T_11 - T_12 T_22^{-1} T_21 (eq. Schur complement in DDRGF, Proposition 4)
 //      on the m w separator layers, as a band of b x b blocks of half bandwidth 2w - 1:
@@ -82,13 +91,37 @@ __device__ __forceinline__ NDWs nd_ws(double2* base, int nmax, int w, size_t bpb
 
 #if defined(RGFK_ND_T0)
 
+// Clears *flag unless the band of H is exactly Hermitian: H_ij = H_ji^H entry by entry
+// for |i - j| <= w (NaN entries count as a mismatch).  Templates, so that every
+// instantiation unit that launches them has them.
+template <int D>
+__global__ void nd_herm_init_kernel(int* flag) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *flag = 1;
+}
+
+template <int D>
+__global__ void nd_herm_check_kernel(const double2* H, int l, int b, int w, int* flag) {
+  const size_t bb = (size_t)b * b;
+  const size_t total = (size_t)(2 * w + 1) * l * bb;
+  for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const int col = (int)(idx % b), row = (int)((idx / b) % b);
+    const int i = (int)((idx / bb) % l);
+    const int d = (int)(idx / (bb * l));       // block (i, i + d - w)
+    const int j = i + d - w;
+    if (j < 0 || j >= l) continue;
+    const double2 x = H[idx];
+    const double2 y = H[((size_t)(2 * w - d) * l + j) * bb + (size_t)col * b + row];   // block (j, i), transposed
+    if (!(x.x == y.x && x.y == -y.y)) *flag = 0;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // 1. interiors
 // ---------------------------------------------------------------------------
-template <int T, int NW>
-__global__ __launch_bounds__(64 * NW, 1) void nddrgf_interior_kernel(NDDArgs a) {
+template <int T, int NW, bool HERM>
+__device__ __forceinline__ void nd_interior(const NDDArgs& a, GJShared& sh) {
   constexpr int BP = 16 * T;
-  __shared__ GJShared sh;
   const int c = blockIdx.x;
   const int e = c / a.m, k = c % a.m;
   const int w = a.w, b = a.b, l = a.l;
@@ -114,6 +147,8 @@ __global__ __launch_bounds__(64 * NW, 1) void nddrgf_interior_kernel(NDDArgs a) 
   auto P = [&](const double2* p) { return opnd(p, BP, BP, BP); };
   auto Pb = [&](const double2* p) { return opnd(p, b, b, b); };
   auto X = [&](int i, int j) { return Pb(Gb(a0 + i, a0 + j)); };
+  // Q_i[s][t] (stored, or P_i[t][s]^H on the Hermitian path)
+  auto Qop = [&](int i, int s, int t) { return HERM ? opnd(Pk(i, t, s), BP, BP, BP, 1) : P(Qk(i, s, t)); };
   Acc<T, NW> acc;
   int bad_layer = -1;
 
@@ -135,6 +170,7 @@ __global__ __launch_bounds__(64 * NW, 1) void nddrgf_interior_kernel(NDDArgs a) 
       const int gi = a0 + n - w + t, gq = pR + s;
       if (s <= t) load<T, NW>(acc, Pb(Hb(gi, gq)), -1.0); else acc_zero<T, NW>(acc);
       store<T, NW>(acc, Pk(n - 1, t, s), BP, BP, BP);
+      if (HERM) continue;
       if (s <= t) load<T, NW>(acc, Pb(Hb(gq, gi)), -1.0); else acc_zero<T, NW>(acc);
       store<T, NW>(acc, Qk(n - 1, s, t), BP, BP, BP);
     }
@@ -170,6 +206,7 @@ __global__ __launch_bounds__(64 * NW, 1) void nddrgf_interior_kernel(NDDArgs a) 
           if (t >= 1) load<T, NW>(acc, P(Pk(i, t - 1, s))); else acc_zero<T, NW>(acc);
           if (cc >= 0) mma<T, NW>(acc, P(Ub(cc, i)), P(Pk(i, w - 1, s)), -1.0);
           store<T, NW>(acc, Pk(i - 1, t, s), BP, BP, BP);
+          if (HERM) continue;
           if (t >= 1) load<T, NW>(acc, P(Qk(i, s, t - 1))); else acc_zero<T, NW>(acc);
           if (cc >= 0) mma<T, NW>(acc, P(Qk(i, s, w - 1)), P(Lb(i, cc)), -1.0);
           store<T, NW>(acc, Qk(i - 1, s, t), BP, BP, BP);
@@ -192,7 +229,7 @@ __global__ __launch_bounds__(64 * NW, 1) void nddrgf_interior_kernel(NDDArgs a) 
       acc_zero<T, NW>(acc);
       for (int t = 0; t < w; ++t) {
         const int cc = i - w + 1 + t;
-        if (cc >= 0) mma<T, NW>(acc, P(Qk(i, s, t)), X(cc, i), 1.0);
+        if (cc >= 0) mma<T, NW>(acc, Qop(i, s, t), X(cc, i), 1.0);
       }
       store<T, NW>(acc, Hx(W.RR, i, s), BP, BP, BP);
     }
@@ -246,6 +283,21 @@ __global__ __launch_bounds__(64 * NW, 1) void nddrgf_interior_kernel(NDDArgs a) 
     __syncthreads();
   }
   if (threadIdx.x == 0) a.info_part[(size_t)e * a.m + k] = bad_layer >= 0 ? bad_layer + 1 : 0;
+}
+
+// Whether interior k takes the Hermitian path: H found exactly Hermitian on the
+// device, eta_d = 0, and no lead in the interior (k > 0).
+__device__ __forceinline__ bool nd_herm_interior(const NDDArgs& a, int k) {
+  return a.herm != nullptr && *a.herm != 0 && a.eta_d == 0.0 && k > 0;
+}
+
+template <int T, int NW>
+__global__ __launch_bounds__(64 * NW, 1) void nddrgf_interior_kernel(NDDArgs a) {
+  __shared__ GJShared sh;
+  if (nd_herm_interior(a, blockIdx.x % a.m))
+    nd_interior<T, NW, true>(a, sh);
+  else
+    nd_interior<T, NW, false>(a, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -441,6 +493,14 @@ template <int T>
 hipError_t launch_nd_T(const NDDArgs& a, const NSweepArgs& red, hipStream_t s) {
   constexpr int NW = T >= 7 ? 8 : 4;
   const int chains = a.ne * a.m;
+  if (a.herm) {
+    hipLaunchKernelGGL(nd_herm_init_kernel<0>, dim3(1), dim3(64), 0, s, a.herm);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(nd_herm_check_kernel<0>, dim3(1024), dim3(256), 0, s, a.H, a.l, a.b, a.w, a.herm);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    ktime_mark("nd_herm_check_kernel", s);
+  }
   hipLaunchKernelGGL((nddrgf_interior_kernel<T, NW>), dim3(chains), dim3(64 * NW), 0, s, a);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;

@@ -43,11 +43,32 @@ def test_ddrgf_ndiagonal(lib, l, b, w, m, form):
     check_dd(f"ddrgf/{form} l={l} b={b} w={w} m={m}", G, T, range(2), refs, oracle_results("dense", wl, range(2)), w)
 
 
+@pytest.mark.parametrize("case", ["non_hermitian", "eta_d"])
+def test_ddrgf_ndiagonal_native_general_path(lib, case):
+    """Native n-diagonal DDRGF on its general interior path: H not Hermitian, or a
+    device broadening eta_d > 0 (the Hermitian path needs both), against the oracle's
+    DDRGF and the dense inverse."""
+    wl = make_random(30, 24, 2, 2, seed=2100, eta=1e-3)
+    eta_d = 0.0
+    if case == "non_hermitian":
+        rng = np.random.default_rng(7)
+        wl.H[3, :29] += 0.05 * (rng.standard_normal((29, 24, 24)) + 1j * rng.standard_normal((29, 24, 24)))
+        wl.H[0, 9, 2, 3] += 0.1
+    else:
+        eta_d = 0.02
+    wl.eta_d = eta_d
+    G, T, info = run_gpu(lib, wl, method="ddrgf", domains=4)
+    assert np.all(info == 0)
+    refs = oracle_results("ddrgf", wl, range(2), m=4)
+    check_dd(f"ddrgf/native general ({case})", G, T, range(2), refs, oracle_results("dense", wl, range(2)), 2)
+
+
 @pytest.mark.parametrize("l,b,w,m", [(16, 100, 2, 3), (21, 128, 2, 2), (26, 40, 4, 3), (17, 7, 3, 2),
-                                     (9, 16, 2, 2), (45, 33, 2, 7)])
+                                     (9, 16, 2, 2), (45, 33, 2, 7), (100, 8, 2, 2), (160, 4, 3, 3)])
 def test_ddrgf_ndiagonal_native_only(lib, l, b, w, m):
     """Native n-diagonal DDRGF where the super-block form cannot run (w b > 128 or l
-    not a multiple of w), with ragged interiors, against the oracle's DDRGF (same
+    not a multiple of w), with ragged interiors and interiors of tens of layers (where
+    an unstable Hermitian shortcut would show), against the oracle's DDRGF (same
     layout) and the dense inverse."""
     wl = make_random(l, b, w, 2, seed=1900 + l + b + w + m, eta=1e-3)
     G, T, info = run_gpu(lib, wl, method="ddrgf", domains=m)
