@@ -15,7 +15,9 @@ pytestmark = pytest.mark.gpu
 def run_ml(lib, wl, m, m2, eta_d=None, ne=None):
     import torch
     H, sL, sR, E = to_dev(wl)
-    plan = lib.Plan(wl.l, wl.b, wl.w, wl.ne, method="ddrgf", domains=m, inner_domains=m2)
+    # two levels for w > 1 run on the w-layer super-block form
+    plan = lib.Plan(wl.l, wl.b, wl.w, wl.ne, method="ddrgf", domains=m, inner_domains=m2,
+                    ddrgf_form="fused" if wl.w > 1 else "native")
     G, T, info = lib.solve(H, sL, sR, E, eta_d=wl.eta_d if eta_d is None else eta_d, plan=plan)
     torch.cuda.synchronize()
     plan.close()
