@@ -25,7 +25,7 @@ namespace rgfk {
 #if defined(RGFK_INST_T) && (RGFK_INST_T == 4 || RGFK_INST_T == 8)
 
 template <int T, int K, int NW>
-__global__ __launch_bounds__(64 * NW, 1) void rgf_split_kernel(SweepArgs a) {
+__global__ __launch_bounds__(64 * NW, (T == 4 && K == 4) ? 2 : 1) void rgf_split_kernel(SweepArgs a) {
   constexpr int BP = 16 * T;
   constexpr int TR = T / K;
   __shared__ GJShared sh;
