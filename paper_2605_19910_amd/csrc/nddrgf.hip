@@ -292,7 +292,7 @@ __device__ __forceinline__ bool nd_herm_interior(const NDDArgs& a, int k) {
 }
 
 template <int T, int NW>
-__global__ __launch_bounds__(64 * NW, 1) void nddrgf_interior_kernel(NDDArgs a) {
+__global__ __launch_bounds__(64 * NW, T == 4 ? 2 : 1) void nddrgf_interior_kernel(NDDArgs a) {
   __shared__ GJShared sh;
   if (nd_herm_interior(a, blockIdx.x % a.m))
     nd_interior<T, NW, true>(a, sh);
