@@ -64,12 +64,14 @@ def test_ddrgf_ndiagonal_native_general_path(lib, case):
 
 
 @pytest.mark.parametrize("l,b,w,m", [(16, 100, 2, 3), (21, 128, 2, 2), (26, 40, 4, 3), (17, 7, 3, 2),
-                                     (9, 16, 2, 2), (45, 33, 2, 7), (100, 8, 2, 2), (160, 4, 3, 3)])
+                                     (9, 16, 2, 2), (45, 33, 2, 7), (100, 8, 2, 2), (160, 4, 3, 3),
+                                     (6, 8, 2, 1), (8, 12, 2, 2), (9, 5, 4, 1)])
 def test_ddrgf_ndiagonal_native_only(lib, l, b, w, m):
     """Native n-diagonal DDRGF where the super-block form cannot run (w b > 128 or l
-    not a multiple of w), with ragged interiors and interiors of tens of layers (where
-    an unstable Hermitian shortcut would show), against the oracle's DDRGF (same
-    layout) and the dense inverse."""
+    not a multiple of w), with ragged interiors, interiors of tens of layers (where
+    an unstable Hermitian shortcut would show), interiors of exactly w layers and a
+    single pair (reduced system of w layers, narrower than its band), against the
+    oracle's DDRGF (same layout) and the dense inverse."""
     wl = make_random(l, b, w, 2, seed=1900 + l + b + w + m, eta=1e-3)
     G, T, info = run_gpu(lib, wl, method="ddrgf", domains=m)
     assert np.all(info == 0)
@@ -147,3 +149,17 @@ def test_config3_distance_to_exact(lib):
         assert eg <= tol and tg <= tol, (e, eg, tg, tol)
     del Gd
     free_gpu()
+
+
+def test_ddrgf_ndiagonal_native_singular_pivot(lib):
+    """Native n-diagonal DDRGF, a closed interior whose last layer is exactly E I - H = 0
+    at the first energy: that interior's first pivot is singular, its global layer is
+    reported, the energy's band and T are NaN, and the other energy is unaffected."""
+    wl = make_random(14, 8, 2, 2, seed=9, eta=1e-3)
+    # 2 pairs, w = 2: interiors [0..4], [7..11]; separators [5, 6], [12, 13]
+    wl.H[2, 11] = wl.energies[0] * np.eye(8)
+    G, T, info = run_gpu(lib, wl, method="ddrgf", domains=2)
+    assert info[0] == 12 and info[1] == 0
+    assert np.all(np.isnan(G[0])) and np.isnan(T[0])
+    refs = oracle_results("ddrgf", wl, [1], m=2)
+    check_dd("ddrgf/native singular neighbour", G, T, [1], refs, oracle_results("dense", wl, [1]), 2)
