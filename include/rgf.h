@@ -180,6 +180,22 @@ rgf_status_t rgf_lead_self_energy(int64_t block_size, int64_t num_energies, cons
                                   int32_t max_steps, void* sigma, int32_t* steps, void* workspace,
                                   size_t workspace_bytes, void* stream);
 
+/* Observables read off a solved band (the densities the Dyson and Keldysh stages
+ * give, Sec. 1 and the outlook): both read only the diagonal blocks of a band in
+ * the layout of G, [nE][2w+1][l][b][b] (DEVICE), and are asynchronous on stream.
+ *   rgf_dos:     dos[e][i b + s] = -(1/pi) Im G^R_{ii,ss}(E_e), the orbital-resolved
+ *                density of states (DEVICE out [nE][l b]);
+ *   rgf_density: density[i b + s] = sum_e weights[e] (1/2pi) Im G^<_{ii,ss}(E_e), the
+ *                orbital-resolved electron density by the caller's quadrature weights
+ *                (DEVICE [nE], e.g. the energy spacing); energies are summed in order,
+ *                so the result is deterministic (DEVICE out [l b]).
+ * Errors: l, b, w, nE >= 1 and non-NULL pointers, else RGF_ERR_INVALID_ARG.  NaN
+ * entries of an energy whose info is nonzero propagate. */
+rgf_status_t rgf_dos(const void* G, int64_t num_layers, int64_t block_size, int64_t half_bandwidth,
+                     int64_t num_energies, double* dos, void* stream);
+rgf_status_t rgf_density(const void* G_lesser, int64_t num_layers, int64_t block_size, int64_t half_bandwidth,
+                         int64_t num_energies, const double* weights, double* density, void* stream);
+
 /* Several workgroups per energy for rgf_solve.  With fewer energies than compute
  * units, the sequential sweep (Algorithm 1 for w = 1, the n-diagonal sweep of Sec.
  * 2.3 for w > 1; FP64, plans without want_backward, padded block size 64 or 128)

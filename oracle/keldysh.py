@@ -51,3 +51,25 @@ def lesser(H, E, sigma_L, sigma_R, f_L: float, f_R: float, eta_d=0.0):
             if 0 <= j < l:
                 out[1 + k, i] = c0[i] @ sl_L @ c0[j].conj().T + cL[i] @ sl_R @ cL[j].conj().T
     return res["G"], out
+
+
+# ----------------------------------------------------------------------------
+# Observables on a solved band (the densities the Dyson and Keldysh stages give)
+# ----------------------------------------------------------------------------
+
+def dos(G_band: np.ndarray, w: int) -> np.ndarray:
+    """Orbital-resolved density of states of one energy, -(1/pi) Im G^R_{ii,ss},
+    from the diagonal blocks of a band [2w+1, l, b, b]; returns [l * b]."""
+    diag = G_band[w]
+    return -np.imag(np.diagonal(diag, axis1=1, axis2=2)).reshape(-1) / np.pi
+
+
+def density(Gless_bands, weights, w: int) -> np.ndarray:
+    """Orbital-resolved electron density, the energy quadrature
+    sum_e weights[e] (1/2pi) Im G^<_{ii,ss}(E_e) (G^<_ss = i a with a >= 0, so
+    -i G^<_ss / 2pi is the spectral density of occupied states); [l * b]."""
+    out = None
+    for g, wt in zip(Gless_bands, weights):
+        x = wt * np.imag(np.diagonal(g[w], axis1=1, axis2=2)).reshape(-1) / (2.0 * np.pi)
+        out = x if out is None else out + x
+    return out

@@ -114,6 +114,10 @@ def load() -> ctypes.CDLL:
     lib.rgf_lead_self_energy.argtypes = [ctypes.c_int64, ctypes.c_int64, _VP, _VP, _VP, _VP, ctypes.c_double,
                                          ctypes.c_double, ctypes.c_int32, _VP, _VP, _VP, ctypes.c_size_t, _VP]
     lib.rgf_lead_self_energy.restype = ctypes.c_int
+    lib.rgf_dos.argtypes = [_VP, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, _VP, _VP]
+    lib.rgf_dos.restype = ctypes.c_int
+    lib.rgf_density.argtypes = [_VP, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, _VP, _VP, _VP]
+    lib.rgf_density.restype = ctypes.c_int
     lib.rgf_plan_set_split.argtypes = [_VP, ctypes.c_int32, ctypes.c_int64]
     lib.rgf_plan_set_split.restype = ctypes.c_int
     lib.rgf_plan_split_workgroups.argtypes = [_VP, ctypes.POINTER(ctypes.c_int32)]
@@ -284,6 +288,41 @@ def lead_self_energy(H00, H01, Hc, energies, eta: float, tolerance: float = 1e-1
     if st != RGF_OK:
         raise RgfError("rgf_lead_self_energy", st)
     return sigma, steps
+
+
+def dos(G, stream: Optional[int] = None):
+    """Orbital-resolved density of states -(1/pi) Im G^R_{ii,ss} of every energy
+    (rgf_dos).  G: complex128 band [nE, 2w+1, l, b, b] on the GPU; returns [nE, l b]."""
+    import torch
+    lib = load()
+    ne, nb, l, b, _ = G.shape
+    if G.dtype != torch.complex128 or not G.is_cuda or not G.is_contiguous():
+        raise ValueError("G must be a contiguous complex128 GPU tensor")
+    out = torch.empty((ne, l * b), dtype=torch.float64, device=G.device)
+    st = lib.rgf_dos(_ptr(G), l, b, (nb - 1) // 2, ne, _ptr(out),
+                     torch.cuda.current_stream(G.device).cuda_stream if stream is None else stream)
+    if st != RGF_OK:
+        raise RgfError("rgf_dos", st)
+    return out
+
+
+def density(G_lesser, weights, stream: Optional[int] = None):
+    """Orbital-resolved electron density sum_e weights[e] Im G^<_{ii,ss}(E_e) / 2pi
+    (rgf_density).  G_lesser: complex128 band [nE, 2w+1, l, b, b] on the GPU; weights:
+    float64 [nE] on the GPU; returns [l b]."""
+    import torch
+    lib = load()
+    ne, nb, l, b, _ = G_lesser.shape
+    if G_lesser.dtype != torch.complex128 or not G_lesser.is_cuda or not G_lesser.is_contiguous():
+        raise ValueError("G_lesser must be a contiguous complex128 GPU tensor")
+    if weights.dtype != torch.float64 or not weights.is_cuda or weights.shape[0] != ne:
+        raise ValueError("weights must be a float64 GPU tensor of one value per energy")
+    out = torch.empty((l * b,), dtype=torch.float64, device=G_lesser.device)
+    st = lib.rgf_density(_ptr(G_lesser), l, b, (nb - 1) // 2, ne, _ptr(weights), _ptr(out),
+                         torch.cuda.current_stream(G_lesser.device).cuda_stream if stream is None else stream)
+    if st != RGF_OK:
+        raise RgfError("rgf_density", st)
+    return out
 
 
 def rgf_backward(plan: Plan, H, sigma_L, sigma_R, energies, eta_d: float, G_diag, g_diag_stride: int, dL_dT,

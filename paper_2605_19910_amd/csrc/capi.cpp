@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include "../../include/rgf.h"
+#include "epilogue.h"
 #include "kernels.h"
 
 struct rgf_plan_s {
@@ -882,5 +883,32 @@ const char* rgf_status_string(rgf_status_t s) {
 }
 
 int rgf_version(void) { return 200; }
+
+
+rgf_status_t rgf_dos(const void* G, int64_t num_layers, int64_t block_size, int64_t half_bandwidth,
+                     int64_t num_energies, double* dos, void* stream) {
+  if (!G || !dos || num_layers < 1 || block_size < 1 || half_bandwidth < 1 || num_energies < 1)
+    return RGF_ERR_INVALID_ARG;
+  if (num_layers > (int64_t)1 << 24 || block_size > 4096 || num_energies > (int64_t)1 << 24 || half_bandwidth > 64)
+    return RGF_ERR_INVALID_ARG;
+  return rgfk::launch_dos(static_cast<const double2*>(G), (int)num_layers, (int)block_size, (int)half_bandwidth,
+                          (int)num_energies, dos, static_cast<hipStream_t>(stream)) == hipSuccess
+             ? RGF_OK
+             : RGF_ERR_HIP;
+}
+
+rgf_status_t rgf_density(const void* G_lesser, int64_t num_layers, int64_t block_size, int64_t half_bandwidth,
+                         int64_t num_energies, const double* weights, double* density, void* stream) {
+  if (!G_lesser || !weights || !density || num_layers < 1 || block_size < 1 || half_bandwidth < 1 ||
+      num_energies < 1)
+    return RGF_ERR_INVALID_ARG;
+  if (num_layers > (int64_t)1 << 24 || block_size > 4096 || num_energies > (int64_t)1 << 24 || half_bandwidth > 64)
+    return RGF_ERR_INVALID_ARG;
+  return rgfk::launch_density(static_cast<const double2*>(G_lesser), (int)num_layers, (int)block_size,
+                              (int)half_bandwidth, (int)num_energies, weights, density,
+                              static_cast<hipStream_t>(stream)) == hipSuccess
+             ? RGF_OK
+             : RGF_ERR_HIP;
+}
 
 }  // extern "C"

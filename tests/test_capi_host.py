@@ -230,3 +230,15 @@ def test_native_ndiagonal_ddrgf_workspace(l, b, w, m, ne):
             + al(ne * 4 * B) + al(ne * m * 4) + al(ne * 4) + al(4))
     assert p.workspace_bytes == want
     p.close()
+
+
+def test_dos_density_argument_errors():
+    """Invalid arguments are rejected before any GPU work."""
+    lib = _lib().load()
+    fake = ctypes.c_void_p(16)
+    assert lib.rgf_dos(None, 4, 4, 1, 2, fake, None) == 1
+    assert lib.rgf_dos(fake, 0, 4, 1, 2, fake, None) == 1
+    assert lib.rgf_dos(fake, 4, 4, 0, 2, fake, None) == 1
+    assert lib.rgf_dos(fake, 4, 4, 1, 0, fake, None) == 1
+    assert lib.rgf_density(fake, 4, 4, 1, 2, None, fake, None) == 1
+    assert lib.rgf_density(fake, 4, 0, 1, 2, fake, fake, None) == 1

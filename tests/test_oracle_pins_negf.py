@@ -170,3 +170,59 @@ def test_lesser_uniform_chain_closed_form():
                         d = 1j * s ** (l - 1 - i) * np.conj(s) ** (l - 1 - j) * gam / np.abs(r) ** 2
                     want = (V * d[None, :]) @ V.conj().T
                     assert np.linalg.norm(Gl[1 + k, i] - want) <= 1e-10 * max(1e-300, np.linalg.norm(want)) + 1e-13
+
+
+def test_dos_uniform_chain_closed_form():
+    """A segment of the uniform chain with eta_d = eta is the infinite chain seen on l
+    layers, whose on-site Green's function is V diag(1 / r_c) V^H with
+    r_c = sqrt(z - eps_c - 2) sqrt(z - eps_c + 2): the DOS of every orbital is
+    -(1/pi) Im (V diag(1 / r_c) V^H)_ss, and a layer's total is sum_c -(1/pi) Im(1/r_c),
+    which for eta -> 0 inside a channel's band is 1 / (pi sqrt(4 - (E - eps_c)^2))."""
+    l, b = 24, 8
+    wl = make_uniform_chain(l, b, 5, seed=106, eta=1e-2, eta_d=1e-2)
+    V, eps = wl.meta["V"], wl.meta["eps"]
+    for e in range(wl.ne):
+        z = wl.energies[e] + 1j * wl.eta - eps
+        r = np.sqrt(z - 2.0) * np.sqrt(z + 2.0)
+        want = -np.imag(np.diagonal((V / r[None, :]) @ V.conj().T)) / np.pi
+        G = oracle.rgf(wl.H, wl.energies[e], wl.sigma_L[e], wl.sigma_R[e], wl.eta_d)["G"]
+        d = oracle.dos(G, 1).reshape(l, b)
+        assert np.max(np.abs(d - want[None, :])) <= 1e-10 * np.max(np.abs(want))
+        assert np.allclose(d.sum(axis=1), np.sum(-np.imag(1.0 / r)) / np.pi, rtol=1e-10)
+    # the eta -> 0 limit of one channel inside its band
+    x = 0.7
+    zz = x + 1e-9j
+    assert abs(-np.imag(1.0 / (np.sqrt(zz - 2.0) * np.sqrt(zz + 2.0))) / np.pi
+               - 1.0 / (np.pi * np.sqrt(4.0 - x * x))) < 1e-7
+
+
+def test_density_equilibrium_is_occupation_times_dos():
+    """With both leads at the same occupation f(E) and no device broadening,
+    G^< = i f A with A = i (G^R - G^A) = -2 Im-part on the diagonal, so the density is
+    sum_e w_e f_e dos_e orbital by orbital (the definition of G^< via the dense inverse
+    on one side, the DOS of the RGF band on the other)."""
+    wl = make_random(8, 5, 1, 6, seed=12, eta=1e-3)
+    f = 1.0 / (1.0 + np.exp((wl.energies - 0.1) / 0.3))
+    wts = np.full(wl.ne, 4.0 / wl.ne)
+    bands, want = [], 0.0
+    for e in range(wl.ne):
+        bands.append(oracle.lesser_dense(wl.H, 1, wl.energies[e], wl.sigma_L[e], wl.sigma_R[e], f[e], f[e], 0.0))
+        G = oracle.rgf(wl.H, wl.energies[e], wl.sigma_L[e], wl.sigma_R[e], 0.0)["G"]
+        want = want + wts[e] * f[e] * oracle.dos(G, 1)
+    got = oracle.density(bands, wts, 1)
+    assert np.max(np.abs(got - want)) <= 1e-11 * np.max(np.abs(want))
+    assert np.all(got > 0)
+
+
+def test_density_dos_pick_the_diagonal():
+    """A planted band: the DOS and density read the s-th diagonal entry of the diagonal
+    blocks only (an off-diagonal entry or block changes nothing)."""
+    l, b, w = 3, 2, 2
+    G = np.zeros((2 * w + 1, l, b, b), dtype=np.complex128)
+    for i in range(l):
+        for s in range(b):
+            G[w, i, s, s] = 1.0 - 1j * (1 + i * b + s)
+    G[w, 1, 0, 1] = 5j
+    G[w + 1, 0] = 7j
+    assert np.allclose(oracle.dos(G, w), np.arange(1, l * b + 1) / np.pi)
+    assert np.allclose(oracle.density([G, 2 * G], [0.5, 0.25], w), -np.arange(1, l * b + 1) / (2 * np.pi))
