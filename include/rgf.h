@@ -195,6 +195,16 @@ rgf_status_t rgf_dos(const void* G, int64_t num_layers, int64_t block_size, int6
                      int64_t num_energies, double* dos, void* stream);
 rgf_status_t rgf_density(const void* G_lesser, int64_t num_layers, int64_t block_size, int64_t half_bandwidth,
                          int64_t num_energies, const double* weights, double* density, void* stream);
+/* Spectral particle current through every bond (w = 1; hbar = 1, spin not counted):
+ * current[e][i] = (1/pi) Re Tr[H_{i,i+1} G^<_{i+1,i}(E_e)], the rate at which charge of
+ * layer i flows to layer i+1 per unit energy (from rho = <c^dag c> = -i int dE/2pi G^<).
+ * In steady state without device broadening it is the same for every bond and equals
+ * T(E) (f_L - f_R) / 2pi.  H: DEVICE band [3][l][b][b] (as for rgf_solve);
+ * G_lesser: DEVICE [nE][3][l][b][b] (rgf_solve_lesser); current: DEVICE out
+ * [nE][l-1].  Errors: l >= 2, b, nE >= 1 and non-NULL pointers, else
+ * RGF_ERR_INVALID_ARG. */
+rgf_status_t rgf_bond_current(const void* H, const void* G_lesser, int64_t num_layers, int64_t block_size,
+                              int64_t num_energies, double* current, void* stream);
 
 /* Several workgroups per energy for rgf_solve.  With fewer energies than compute
  * units, the sequential sweep (Algorithm 1 for w = 1, the n-diagonal sweep of Sec.

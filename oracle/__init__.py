@@ -31,5 +31,5 @@ from .ext_precision import (  # noqa: F401
     solve_energy_ext,
     transmission_ext,
 )
-from .keldysh import density, dos, lesser, lesser_dense  # noqa: F401,E402
+from .keldysh import bond_current, density, dos, lesser, lesser_dense  # noqa: F401,E402
 from .leads import lead_self_energies, lead_self_energy, surface_gf  # noqa: F401,E402

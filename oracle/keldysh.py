@@ -73,3 +73,15 @@ def density(Gless_bands, weights, w: int) -> np.ndarray:
         x = wt * np.imag(np.diagonal(g[w], axis1=1, axis2=2)).reshape(-1) / (2.0 * np.pi)
         out = x if out is None else out + x
     return out
+
+
+def bond_current(H: np.ndarray, Gless_band: np.ndarray) -> np.ndarray:
+    """Spectral particle current from layer i to layer i+1 at one energy (w = 1,
+    hbar = 1, spin not counted): with rho = <c^dag c> = -i int dE/2pi G^<, the rate
+    of change of the charge on layer i through the bond (i, i+1) gives
+    j_i(E) = (1/pi) Re Tr[H_{i,i+1} G^<_{i+1,i}(E)]; returns [l - 1]."""
+    l = H.shape[1]
+    out = np.empty(l - 1)
+    for i in range(l - 1):
+        out[i] = np.real(np.trace(H[2, i] @ Gless_band[0, i + 1])) / np.pi
+    return out

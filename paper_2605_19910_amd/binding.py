@@ -118,6 +118,8 @@ def load() -> ctypes.CDLL:
     lib.rgf_dos.restype = ctypes.c_int
     lib.rgf_density.argtypes = [_VP, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, _VP, _VP, _VP]
     lib.rgf_density.restype = ctypes.c_int
+    lib.rgf_bond_current.argtypes = [_VP, _VP, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, _VP, _VP]
+    lib.rgf_bond_current.restype = ctypes.c_int
     lib.rgf_plan_set_split.argtypes = [_VP, ctypes.c_int32, ctypes.c_int64]
     lib.rgf_plan_set_split.restype = ctypes.c_int
     lib.rgf_plan_split_workgroups.argtypes = [_VP, ctypes.POINTER(ctypes.c_int32)]
@@ -322,6 +324,25 @@ def density(G_lesser, weights, stream: Optional[int] = None):
                          torch.cuda.current_stream(G_lesser.device).cuda_stream if stream is None else stream)
     if st != RGF_OK:
         raise RgfError("rgf_density", st)
+    return out
+
+
+def bond_current(H, G_lesser, stream: Optional[int] = None):
+    """Spectral particle current through every bond (rgf_bond_current), w = 1.
+    H: complex128 band [3, l, b, b]; G_lesser: [nE, 3, l, b, b] (GPU); returns [nE, l-1]."""
+    import torch
+    lib = load()
+    ne, nb, l, b, _ = G_lesser.shape
+    for t, name in ((H, "H"), (G_lesser, "G_lesser")):
+        if t.dtype != torch.complex128 or not t.is_cuda or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous complex128 GPU tensor")
+    if nb != 3 or tuple(H.shape) != (3, l, b, b):
+        raise ValueError("block tridiagonal bands of matching shape are required")
+    out = torch.empty((ne, l - 1), dtype=torch.float64, device=H.device)
+    st = lib.rgf_bond_current(_ptr(H), _ptr(G_lesser), l, b, ne, _ptr(out),
+                              torch.cuda.current_stream(H.device).cuda_stream if stream is None else stream)
+    if st != RGF_OK:
+        raise RgfError("rgf_bond_current", st)
     return out
 
 

@@ -911,4 +911,17 @@ rgf_status_t rgf_density(const void* G_lesser, int64_t num_layers, int64_t block
              : RGF_ERR_HIP;
 }
 
+rgf_status_t rgf_bond_current(const void* H, const void* G_lesser, int64_t num_layers, int64_t block_size,
+                              int64_t num_energies, double* current, void* stream) {
+  if (!H || !G_lesser || !current || num_layers < 2 || block_size < 1 || num_energies < 1)
+    return RGF_ERR_INVALID_ARG;
+  if (num_layers > (int64_t)1 << 20 || block_size > 4096 || num_energies * (num_layers - 1) > ((int64_t)1 << 31) - 1)
+    return RGF_ERR_INVALID_ARG;
+  return rgfk::launch_bond_current(static_cast<const double2*>(H), static_cast<const double2*>(G_lesser),
+                                   (int)num_layers, (int)block_size, (int)num_energies, current,
+                                   static_cast<hipStream_t>(stream)) == hipSuccess
+             ? RGF_OK
+             : RGF_ERR_HIP;
+}
+
 }  // extern "C"

@@ -242,3 +242,6 @@ def test_dos_density_argument_errors():
     assert lib.rgf_dos(fake, 4, 4, 1, 0, fake, None) == 1
     assert lib.rgf_density(fake, 4, 4, 1, 2, None, fake, None) == 1
     assert lib.rgf_density(fake, 4, 0, 1, 2, fake, fake, None) == 1
+    assert lib.rgf_bond_current(fake, fake, 1, 4, 2, fake, None) == 1
+    assert lib.rgf_bond_current(None, fake, 4, 4, 2, fake, None) == 1
+    assert lib.rgf_bond_current(fake, fake, 4, 4, 0, fake, None) == 1

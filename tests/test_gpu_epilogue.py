@@ -1,4 +1,4 @@
-"""Observables read off a solved band on the GPU (rgf_dos, rgf_density): the density
+"""Observables read off a solved band on the GPU (rgf_dos, rgf_density, rgf_bond_current): the density
 of states against the oracle's definition on the same band (bitwise: one division per
 entry) and against the uniform chain's closed form, and the electron density against
 the oracle's and against the equilibrium identity density = sum_e w_e f_e DOS_e.
@@ -7,7 +7,8 @@ Bounds.  The uniform chain's band is exact on the GPU to ~1e-13 relative (its pi
 are well conditioned), so the closed form is checked at 1e-9 relative.  The equilibrium
 identity holds exactly; both sides come from the same GPU sweep (G^< from its
 multipliers), so they agree to the sweep's rounding times the pivots' conditioning,
-well inside 1e-9 relative for these systems (pivot kappa below 1e4).  Against the
+well inside 1e-9 relative for these systems (pivot kappa below 1e4); the same holds for the
+bond currents against T(E) (f_L - f_R) / 2pi.  Against the
 oracle's density the same 1e-9 holds (FP64 rule of the sweep at b = 16, kappa <= 1e4:
 2 b u kappa ~ 1e-11, summed over a handful of energies)."""
 import numpy as np
@@ -82,3 +83,26 @@ def test_density_equilibrium_and_oracle(lib):
     print(f"density: vs equilibrium identity {e1:.2e}, vs oracle {e2:.2e}", flush=True)
     assert e1 <= 1e-9 and e2 <= 1e-9
     free_gpu()
+
+
+@pytest.mark.parametrize("fL,fR", [(1.0, 0.0), (0.25, 0.75)])
+def test_bond_current_conserved_and_landauer(lib, fL, fR):
+    """Every bond carries T(E) (f_L - f_R) / 2pi (GPU T), and the kernel agrees with the
+    oracle's trace on the same G^< band."""
+    import torch
+    wl = make_random(16, 24, 1, 4, seed=47, eta=1e-3)
+    H, sL, sR, E = to_dev(wl.H, wl.sigma_L, wl.sigma_R, wl.energies)
+    fl, fr = to_dev(np.full(wl.ne, fL), np.full(wl.ne, fR))
+    G, Gl, T, info = lib.solve_lesser(H, sL, sR, E, fl, fr, eta_d=0.0)
+    j = lib.bond_current(H, Gl)
+    torch.cuda.synchronize()
+    assert bool((info == 0).all())
+    jh, Th, Glh = j.cpu().numpy(), T.cpu().numpy(), Gl.cpu().numpy()
+    worst_id = worst_or = 0.0
+    for e in range(wl.ne):
+        want = Th[e] * (fL - fR) / (2 * np.pi)
+        worst_id = max(worst_id, np.max(np.abs(jh[e] - want)) / max(abs(want), 1e-3))
+        ref = oracle.bond_current(wl.H, Glh[e])
+        worst_or = max(worst_or, np.max(np.abs(jh[e] - ref)) / max(np.max(np.abs(ref)), 1e-3))
+    print(f"bond current: vs Landauer {worst_id:.2e}, vs oracle trace {worst_or:.2e}", flush=True)
+    assert worst_id <= 1e-9 and worst_or <= 1e-12

@@ -226,3 +226,29 @@ def test_density_dos_pick_the_diagonal():
     G[w + 1, 0] = 7j
     assert np.allclose(oracle.dos(G, w), np.arange(1, l * b + 1) / np.pi)
     assert np.allclose(oracle.density([G, 2 * G], [0.5, 0.25], w), -np.arange(1, l * b + 1) / (2 * np.pi))
+
+
+@pytest.mark.parametrize("fL,fR", [(1.0, 0.0), (0.3, 0.8)])
+def test_bond_current_is_conserved_and_landauer(fL, fR):
+    """In steady state without device broadening the particle current is the same
+    through every bond and equals the Landauer current T(E) (f_L - f_R) / 2pi, T the
+    Caroli transmission (a relation between the lesser band and G_{0,l-1} alone)."""
+    wl = make_random(10, 6, 1, 5, seed=21, eta=1e-3)
+    for e in range(wl.ne):
+        G, Gl = oracle.lesser(wl.H, wl.energies[e], wl.sigma_L[e], wl.sigma_R[e], fL, fR, 0.0)
+        r = oracle.rgf(wl.H, wl.energies[e], wl.sigma_L[e], wl.sigma_R[e], 0.0)
+        T = oracle.transmission(r["row0"][wl.l - 1], wl.sigma_L[e], wl.sigma_R[e])
+        j = oracle.bond_current(wl.H, Gl)
+        want = T * (fL - fR) / (2 * np.pi)
+        assert np.max(np.abs(j - want)) <= 1e-10 * max(abs(want), 1e-3), (e, j, want)
+
+
+def test_bond_current_uniform_chain_counts_channels():
+    """Uniform chain, leads (1, 0): every bond carries (open channels) / 2pi."""
+    wl = make_uniform_chain(12, 8, 6, seed=106, eta=1e-6)
+    eps = wl.meta["eps"]
+    for e in range(wl.ne):
+        _, Gl = oracle.lesser(wl.H, wl.energies[e], wl.sigma_L[e], wl.sigma_R[e], 1.0, 0.0, 0.0)
+        j = oracle.bond_current(wl.H, Gl)
+        n_open = np.sum(np.abs(wl.energies[e] - eps) < 2)
+        assert np.max(np.abs(j - n_open / (2 * np.pi))) < 1e-6
