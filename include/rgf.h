@@ -240,7 +240,7 @@ rgf_status_t ddrgf_solve(rgf_plan_t plan, const void* H, const void* sigma_L, co
  * Batched launch over systems ("devices") of uneven size
  * ---------------------------------------------------------------------------
  * Each device d has its own block-tridiagonal band H_d (l_d layers of b_d orbitals,
- * b_d a multiple of 16 up to 128) and its own energies; one instance = one (device,
+ * 1 <= b_d <= 128) and its own energies; one instance = one (device,
  * energy) pair.  All instances run in ONE persistent kernel: workgroups pull
  * instances from a work queue ordered by the plan's schedule and run the whole
  * sweep of each (Algorithm 1); the outputs are T(E) and the diagonal blocks G_ii
@@ -251,7 +251,7 @@ rgf_status_t ddrgf_solve(rgf_plan_t plan, const void* H, const void* sigma_L, co
 /* Host-side shape of one device. */
 typedef struct {
   int64_t num_layers;     /* l_d >= 1 */
-  int64_t block_size;     /* b_d a multiple of 16 in [16, 128] */
+  int64_t block_size;     /* b_d in [1, 128] (padded to a multiple of 16 inside) */
   int64_t num_energies;   /* nE_d >= 1 */
 } rgf_batch_shape_t;
 

@@ -320,8 +320,9 @@ rgf_status_t rgf_batched_plan_create(int64_t num_devices, const rgf_batch_shape_
     const rgf_batch_shape_t& sh = shapes[d];
     if (sh.num_layers < 1 || sh.num_layers > (1 << 20) || sh.num_energies < 1 || sh.num_energies > (1 << 20))
       return RGF_ERR_INVALID_ARG;
-    if (sh.block_size < 16 || sh.block_size > 128 || sh.block_size % 16 != 0) return RGF_ERR_UNSUPPORTED;
-    slot = std::max(slot, rgfk::sweep_ws_chain_elems((int)sh.num_layers, (int)sh.block_size));
+    if (sh.block_size < 1) return RGF_ERR_INVALID_ARG;
+    if (sh.block_size > 128) return RGF_ERR_UNSUPPORTED;
+    slot = std::max(slot, rgfk::sweep_ws_chain_elems((int)sh.num_layers, rgfk::padded_block((int)sh.block_size)));
     const double cost = (double)sh.num_layers * (double)sh.block_size * sh.block_size * sh.block_size;
     for (int64_t e = 0; e < sh.num_energies; ++e) items.push_back({(int)d, (int)e, cost, (int)sh.block_size});
   }
@@ -331,7 +332,7 @@ rgf_status_t rgf_batched_plan_create(int64_t num_devices, const rgf_batch_shape_
   } else if (schedule == RGF_SCHEDULE_INTERLEAVED) {
     // longest first inside each block size, then take one from each size in turn
     std::vector<std::vector<Item>> by(8);
-    for (const Item& it : items) by[it.b / 16 - 1].push_back(it);
+    for (const Item& it : items) by[rgfk::padded_block(it.b) / 16 - 1].push_back(it);
     for (auto& v : by)
       std::stable_sort(v.begin(), v.end(), [](const Item& x, const Item& y) { return x.cost > y.cost; });
     std::vector<size_t> pos(8, 0);

@@ -384,7 +384,7 @@ __global__ __launch_bounds__(64 * NW, 8 / NW) void rgf_batched_kernel(BatchArgs 
     ch.nd = 0;
     ch.dlen = 1;
     ch.kappa_max = a.kappa_max;
-    switch (b >> 4) {
+    switch ((b + 15) >> 4) {
       case 1: run_chain<1, NW, MIXED>(ch, sh, red); break;
       case 2: run_chain<2, NW, MIXED>(ch, sh, red); break;
       case 3: run_chain<3, NW, MIXED>(ch, sh, red); break;

@@ -55,10 +55,12 @@ def test_small_uneven_batch(lib, schedule):
 
 @pytest.mark.parametrize("waves", [8, 4])
 def test_block_sizes_and_tiles(lib, waves):
-    """Every block size that is a multiple of 16 (not only those of the 64-device
-    workload), with one and with two workgroups per compute unit."""
+    """Every padded block size (not only those of the 64-device workload), including
+    sizes that are not multiples of 16, with one and with two workgroups per compute
+    unit."""
     import torch
-    shapes = [(6, 16, 2), (5, 48, 2), (4, 80, 1), (3, 112, 2), (7, 32, 1), (2, 128, 1), (5, 64, 1), (3, 96, 1)]
+    shapes = [(6, 16, 2), (5, 48, 2), (4, 80, 1), (3, 112, 2), (7, 32, 1), (2, 128, 1), (5, 64, 1), (3, 96, 1),
+              (4, 5, 2), (6, 37, 1), (3, 100, 2), (2, 127, 1), (2, 20, 1)]
     wls = [make_random(l, b, 1, ne, seed=3500 + l + b, eta=1e-3) for (l, b, ne) in shapes]
     outs = lib.solve_batched(to_dev(wls), 0.0, waves=waves)
     torch.cuda.synchronize()
