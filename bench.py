@@ -37,11 +37,11 @@ TRAFFIC_SOURCES = ("paper_2605_19910_amd/csrc/block_engine.h", "paper_2605_19910
                    "paper_2605_19910_amd/csrc/split_engine.h", "paper_2605_19910_amd/csrc/rgf_split.hip")
 MEASURED_TRAFFIC = {
     # sequential sweep with 4 workgroups per energy, l=256, b=128, 64 energies: FETCH_SIZE
-    # 2.91863e+07 KiB x 2.00 + WRITE_SIZE 3.40129e+07 KiB x 1.00 (copy calibration: a 1 GiB copy
+    # 2.94817e+07 KiB x 2.00 + WRITE_SIZE 3.40240e+07 KiB x 1.00 (copy calibration: a 1 GiB copy
     # reads 5.2431e+05 and writes 1.0486e+06 KiB); profiles/rgf_split_kernel_b128_l256_e64_counters.txt
     ("rgf_split_kernel", "c2/rgf_fp64"): {
-        "sha256": "6b08ee5bed7a51da5322cd968cb271c05879f5a4f2ade0c7e6000b325dee2769",
-        "bytes": 9.460034e+10},
+        "sha256": "08b7a0d0b028b380cbbc1a7d4ca07569955716f4ea74e9166821577456aaa711",
+        "bytes": 9.521683e+10},
 }
 
 
