@@ -147,10 +147,12 @@ rgf_status_t rgf_solve(rgf_plan_t plan, const void* H, const void* sigma_L, cons
  * energy); a device broadening eta_d enters G^R only.  Then
  *   G^<_ij = G_{i,0} Sigma^<_L G_{j,0}^H + G_{i,l-1} Sigma^<_R G_{j,l-1}^H,
  * with the first and last block columns of G^R from the multipliers of Algorithm
- * 1's sweep.  Runs rgf_solve (same arguments, results and workspace) and then
- * writes G_lesser [nE][3][l][b][b] in the layout of G (blocks outside the matrix
- * are not written; energies whose info is nonzero get NaN).  Sequential plans with
- * w = 1, FP64, without want_backward (else RGF_ERR_UNSUPPORTED). */
+ * 1's sweep (for w > 1: the first column by the sweep's downward recursion, the last
+ * through transfer products of its multipliers, Sec. 2.3).  Runs rgf_solve (same
+ * arguments, results and workspace) and then writes G_lesser [nE][2w+1][l][b][b] in
+ * the layout of G (blocks outside the matrix are not written; energies whose info is
+ * nonzero get NaN).  Sequential FP64 plans without want_backward (else
+ * RGF_ERR_UNSUPPORTED). */
 rgf_status_t rgf_solve_lesser(rgf_plan_t plan, const void* H, const void* sigma_L, const void* sigma_R,
                               const double* energies, double eta_d, const double* occupation_L,
                               const double* occupation_R, void* G, void* G_lesser, double* T, int32_t* info,

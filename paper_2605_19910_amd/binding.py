@@ -242,14 +242,15 @@ def rgf_solve_lesser(plan: Plan, H, sigma_L, sigma_R, energies, eta_d: float, oc
 def solve_lesser(H, sigma_L, sigma_R, energies, occupation_L, occupation_R, eta_d: float = 0.0,
                  plan: Optional[Plan] = None) -> Tuple:
     """Allocate outputs and run rgf_solve_lesser on the current stream.  Returns
-    (G [nE, 3, l, b, b], G_lesser [nE, 3, l, b, b], T [nE], info [nE])."""
+    (G [nE, 2w+1, l, b, b], G_lesser [nE, 2w+1, l, b, b], T [nE], info [nE])."""
     import torch
-    _, l, b, _ = H.shape
+    nb, l, b, _ = H.shape
+    w = (nb - 1) // 2
     ne = energies.shape[0]
     if plan is None:
-        plan = Plan(l, b, 1, ne)
+        plan = Plan(l, b, w, ne)
     dev = H.device
-    G = torch.empty((ne, 3, l, b, b), dtype=torch.complex128, device=dev)
+    G = torch.empty((ne, nb, l, b, b), dtype=torch.complex128, device=dev)
     Gl = torch.empty_like(G)
     T = torch.empty((ne,), dtype=torch.float64, device=dev)
     info = torch.empty((ne,), dtype=torch.int32, device=dev)

@@ -10,6 +10,7 @@
 #include "../../include/rgf.h"
 #include "epilogue.h"
 #include "kernels.h"
+#include "nlesser.h"
 
 struct rgf_plan_s {
   rgf_desc_t d;
@@ -193,8 +194,8 @@ rgf_status_t rgf_plan_create(const rgf_desc_t* desc, rgf_plan_t* plan, size_t* w
   const int w = (int)desc->half_bandwidth;
   if (w == 1)
     p->ws_chain = rgfk::sweep_ws_chain_elems((int)desc->num_layers, p->bp);
-  else
-    p->ws_chain = rgfk::nrgf_ws_chain_elems((int)desc->num_layers, w, p->bp);
+  else  // + the lesser function's 2w last-column transfer blocks
+    p->ws_chain = rgfk::nrgf_ws_chain_elems((int)desc->num_layers, w, p->bp) + (size_t)2 * w * p->bp * p->bp;
   p->ws_bytes = p->ws_chain * sizeof(double2) * (size_t)desc->num_energies;
   if (desc->method == RGF_METHOD_SEQUENTIAL && !desc->want_backward) {
     // group counters of the split sweep, 64 bytes per energy
@@ -537,7 +538,7 @@ rgf_status_t rgf_solve_lesser(rgf_plan_t plan, const void* H, const void* sigma_
   if (!plan) return RGF_ERR_INVALID_ARG;
   if (plan->batched || plan->d.method != RGF_METHOD_SEQUENTIAL) return RGF_ERR_PLAN_MISMATCH;
   const rgf_desc_t& d = plan->d;
-  if (d.half_bandwidth != 1 || d.precision != RGF_FP64 || d.want_backward) return RGF_ERR_UNSUPPORTED;
+  if (d.precision != RGF_FP64 || d.want_backward) return RGF_ERR_UNSUPPORTED;
   if (!occupation_L || !occupation_R || !G_lesser) return RGF_ERR_INVALID_ARG;
   rgf_status_t st = rgf_solve(plan, H, sigma_L, sigma_R, energies, eta_d, G, T, info, workspace,
                               workspace_bytes, stream);
@@ -556,7 +557,10 @@ rgf_status_t rgf_solve_lesser(rgf_plan_t plan, const void* H, const void* sigma_
   a.l = (int)d.num_layers;
   a.b = (int)d.block_size;
   a.ne = (int)d.num_energies;
-  return rgfk::launch_rgf_lesser(a, static_cast<hipStream_t>(stream)) == hipSuccess ? RGF_OK : RGF_ERR_HIP;
+  hipError_t e = d.half_bandwidth == 1
+                     ? rgfk::launch_rgf_lesser(a, static_cast<hipStream_t>(stream))
+                     : rgfk::launch_nrgf_lesser(a, (int)d.half_bandwidth, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? RGF_OK : RGF_ERR_HIP;
 }
 
 rgf_status_t ddrgf_solve(rgf_plan_t plan, const void* H, const void* sigma_L, const void* sigma_R,

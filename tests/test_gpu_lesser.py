@@ -8,11 +8,13 @@ oracle within 2 * fp64_bound(kappa_max, b), relative Frobenius over the band.
 Cases: small ragged systems with random occupations (with and without device
 broadening), the 256 x 128 system at 9 energies with the Fermi functions of two
 leads at different chemical potentials, the uniform chain against its closed form
-at the full size, and a singular pivot.
+at the full size, a singular pivot, and block n-diagonal systems (w = 2, 3, 4, with
+one and several workgroups per energy in the sweep) against the dense definition.
 """
 import numpy as np
 import pytest
 
+import oracle
 from parity import fp64_bound, mask_band, oracle_results, rel
 from test_gpu_rgf import free_gpu, to_dev
 from workloads import make_config, make_random, make_uniform_chain, surface_sigma
@@ -28,7 +30,7 @@ def run(lib, wl, fL, fR, eta_d=0.0, split=0):
     import torch
     H, sL, sR, E = to_dev(wl)
     d = H.device
-    plan = lib.Plan(wl.l, wl.b, 1, wl.ne)
+    plan = lib.Plan(wl.l, wl.b, wl.w, wl.ne)
     plan.set_split(split, 0)
     G, Gl, T, info = lib.solve_lesser(H, sL, sR, E, torch.from_numpy(np.asarray(fL, dtype=np.float64)).to(d),
                                       torch.from_numpy(np.asarray(fR, dtype=np.float64)).to(d), eta_d, plan=plan)
@@ -143,3 +145,27 @@ def test_lesser_rejects_other_plans(lib):
             lib.solve_lesser(H, sL, sR, E, f, f, plan=plan)
         assert ei.value.code == 2
         plan.close()
+
+
+@pytest.mark.parametrize("l,b,w,eta_d", [(7, 8, 2, 0.0), (12, 20, 3, 0.0), (9, 16, 2, 0.05), (20, 37, 2, 0.0),
+                                         (10, 64, 4, 0.0), (6, 128, 2, 0.0), (3, 5, 2, 0.0)])
+def test_lesser_ndiagonal(lib, l, b, w, eta_d):
+    """Block n-diagonal G^< (first column by the sweep's downward recursion, last column
+    through the transfer products of its multipliers) against the dense definition
+    M^{-1} Sigma^< M^{-H}, within twice the FP64 rule of the n-diagonal sweep."""
+    wl = make_random(l, b, w, 3, seed=4300 + l + b + w, eta=1e-3)
+    rng = np.random.default_rng(l * b + w)
+    fL, fR = rng.uniform(0, 1, 3), rng.uniform(0, 1, 3)
+    G, Gl, T, info = run(lib, wl, fL, fR, eta_d)
+    assert bool((info == 0).all())
+    kap = oracle_results("nrgf", wl, range(3), eta_d=eta_d)
+    bad = []
+    for e in range(3):
+        want = oracle.lesser_dense(wl.H, w, wl.energies[e], wl.sigma_L[e], wl.sigma_R[e], fL[e], fR[e], eta_d)
+        err = rel(mask_band(Gl[e].cpu().numpy(), w), want)
+        tol = 2.0 * fp64_bound(kap[e]["kappa"], b)
+        print(f"lesser l={l} b={b} w={w} energy {e}: kappa {kap[e]['kappa']:.2e} |dG<|/|G<| {err:.2e} "
+              f"bound {tol:.2e}", flush=True)
+        if not err <= tol:
+            bad.append((e, err, tol))
+    assert not bad, bad
