@@ -41,7 +41,7 @@ struct rgf_plan_s {
   int ndd = 0;
   size_t nd_int_chain = 0, nd_red_chain = 0;
   size_t offn_int = 0, offn_ms = 0, offn_gs = 0, offn_gslast = 0, offn_red = 0, offn_fin = 0, offn_info = 0,
-         offn_infored = 0, offn_herm = 0;
+         offn_infored = 0, offn_herm = 0, offn_sync = 0;
   // w > 1 DDRGF, super-block form: copies of the inputs and of the output band
   int fl, fb;                    // super-layers and super-block size of the DDRGF system
   size_t off_hf, off_slf, off_srf, off_gf, off_inff;
@@ -243,6 +243,7 @@ rgf_status_t rgf_plan_create(const rgf_desc_t* desc, rgf_plan_t* plan, size_t* w
     p->offn_info = off;    off = align256(off + (size_t)ne * m * sizeof(int));
     p->offn_infored = off; off = align256(off + (size_t)ne * sizeof(int));
     p->offn_herm = off;    off = align256(off + sizeof(int));
+    p->offn_sync = off;    off = align256(off + (size_t)64 * ne);
     p->ws_bytes = off;
   } else if (desc->method == RGF_METHOD_DDRGF) {
     const int l = (int)desc->num_layers / w, m = (int)desc->num_domains, ne = (int)desc->num_energies;
@@ -618,6 +619,11 @@ rgf_status_t ddrgf_solve(rgf_plan_t plan, const void* H, const void* sigma_L, co
     r.ne = a.ne;
     r.nr = w;
     r.rows_last = a.GSlast;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone) {
+      r.sync = reinterpret_cast<unsigned*>(ws + plan->offn_sync);
+      r.spin_limit = DEFAULT_SPLIT_SPIN;
+    }
     return rgfk::launch_nddrgf(a, r, st) == hipSuccess ? RGF_OK : RGF_ERR_HIP;
   }
   rgfk::FuseArgs f{};

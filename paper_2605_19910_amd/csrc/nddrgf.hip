@@ -38,8 +38,9 @@
 //      on the m w separator layers, as a band of b x b blocks of half bandwidth 2w - 1:
 //      the separator diagonal blocks, and the couplings between neighbouring
 //      separators through one interior (the "orange" blocks).
-//   3. the n-diagonal sweep in direct mode on the reduced system: band of G_S and its
-//      first w block rows at the last column.
+//   3. the n-diagonal sweep in direct mode on the reduced system (several workgroups
+//      per energy when they fit): band of G_S and its first w block rows at the last
+//      column.
 //   4. nddrgf_recover_kernel  one workgroup per (energy, interior): Algorithm 2 step 4,
 //        G_{D2,D2} = X + X T_21 G_S T_12 X,  G_{D2,D1} = -X T_21 G_S,  G_{D1,D2} = -G_S T_12 X,
 //      inside the band, added in place; step 5 (inverse reordering) is the index map.
@@ -454,8 +455,11 @@ __global__ __launch_bounds__(64 * NW, 1) void nddrgf_finalize_kernel(NDDArgs a) 
     // first failing pivot in elimination order: interiors, then the reduced system
     int inf = 0;
     for (int k = 0; k < m && inf == 0; ++k) inf = a.info_part[(size_t)e * m + k];
-    if (inf == 0 && a.info_red[e] != 0) {
-      const int r = a.info_red[e] - 1;
+    const int ir = a.info_red[e];
+    if (inf == 0 && (ir & RGF_INFO_SYNC_TIMEOUT)) {
+      inf = RGF_INFO_SYNC_TIMEOUT;   // the split reduced sweep gave up waiting
+    } else if (inf == 0 && ir != 0) {
+      const int r = ir - 1;
       inf = lay.p(r / w) + r % w + 1;
     }
     s_info = inf;
@@ -508,7 +512,10 @@ hipError_t launch_nd_T(const NDDArgs& a, const NSweepArgs& red, hipStream_t s) {
   hipLaunchKernelGGL((nddrgf_schur_kernel<T, NW>), dim3(chains), dim3(64 * NW), 0, s, a);
   if ((err = hipGetLastError()) != hipSuccess) return err;
   ktime_mark("nddrgf_schur_kernel", s);
-  if ((err = launch_nrgf_sweep(red, s)) != hipSuccess) return err;
+  // the reduced system with several workgroups per energy when they fit co-resident
+  // (sync counters given: not under stream capture)
+  const int K = red.sync ? split_workgroups_n(red.b, red.ne, 0) : 1;
+  if ((err = K > 1 ? launch_nrgf_split(red, K, s) : launch_nrgf_sweep(red, s)) != hipSuccess) return err;
   hipLaunchKernelGGL((nddrgf_recover_kernel<T, NW>), dim3(chains), dim3(64 * NW), 0, s, a);
   if ((err = hipGetLastError()) != hipSuccess) return err;
   ktime_mark("nddrgf_recover_kernel", s);

@@ -9,7 +9,8 @@
 // workgroup its own rows) | barrier; per layer of the downward pass: G_{a,i},
 // G_{i,a}, R_i slabs | barrier | G_ii slab | barrier.  Every slab repeats the
 // one-workgroup kernel's operations in the same order, so the results are bitwise
-// those of nrgf_sweep_kernel.
+// those of nrgf_sweep_kernel, also in its direct mode (the reduced separator system
+// of the n-diagonal DDRGF, with its first nr block rows carried to the last column).
 #include "kernels.h"
 #include "split_engine.h"
 
@@ -41,15 +42,18 @@ __global__ __launch_bounds__(64 * NW, (T == 4 && K == 4) ? 2 : 1) void nrgf_spli
   double2* GamL = R + (size_t)l * bpbp;
   double2* GamR = GamL + bpbp;
   double2* X1 = GamR + bpbp;
-  const double2* sL = a.sigL + (size_t)e * bb;
-  const double2* sR = a.sigR + (size_t)e * bb;
+  double2* Rx = X1 + bpbp;                           // rows t >= 1: G_{t,i} at (t-1) l + i
+  const double2* sL = a.direct ? nullptr : a.sigL + (size_t)e * bb;
+  const double2* sR = a.direct ? nullptr : a.sigR + (size_t)e * bb;
+  const double2* Hband = a.H + (a.direct ? (size_t)e * a.h_stride : 0);
   const double2 z = make_double2(a.E[e], a.eta_d);
   double2* Gout = a.G + (size_t)e * (2 * w + 1) * l * bb;
   unsigned* ctr = a.sync + (size_t)e * 16;
   int* info = a.info + e;
 
   auto Sblk = [&](int i, int j) { return Sw + ((size_t)(w + j - i) * l + i) * bpbp; };
-  auto Hblk = [&](int i, int j) { return a.H + ((size_t)(w + j - i) * l + i) * bb; };
+  auto Hblk = [&](int i, int j) { return Hband + ((size_t)(w + j - i) * l + i) * bb; };
+  auto Rrow = [&](int tr, int i) { return Rx + ((size_t)(tr - 1) * l + i) * bpbp; };
   auto Gblk = [&](int i, int j) { return Gout + ((size_t)(w + j - i) * l + i) * bb; };
   auto Ublk = [&](int c, int i) { return U + ((size_t)i * w + (i - c - 1)) * bpbp; };
   auto Lblk = [&](int i, int c) { return L + ((size_t)i * w + (i - c - 1)) * bpbp; };
@@ -70,13 +74,21 @@ __global__ __launch_bounds__(64 * NW, (T == 4 && K == 4) ? 2 : 1) void nrgf_spli
       for (int kk = -w; kk <= w; ++kk) {
         const int j = i + kk;
         if (j < 0 || j >= l) continue;
-        if (kk == 0) {
+        if (a.direct) {
+          sload<TR, T, NW>(sa, Pb(Hblk(i, j)), row0);
+        } else if (kk == 0) {
           sacc_zero<TR, T, NW>(sa);
           sadd_diag<TR, T, NW>(sa, Hblk(i, i), b, z, i == 0 ? sL : nullptr, i == l - 1 ? sR : nullptr, row0);
         } else {
           sload<TR, T, NW>(sa, Pb(Hblk(i, j)), row0, -1.0);
         }
         sstore<TR, T, NW>(sa, Sblk(i, j), BP, BP, BP, row0);
+        if (a.direct && kk == 0 && b < BP) {
+          // identity on the padding of a directly given diagonal block (own rows)
+          __syncthreads();
+          for (int r = row0 + (int)threadIdx.x; r < row0 + 16 * TR; r += 64 * NW)
+            if (r >= b) Sblk(i, i)[(size_t)r * BP + r] = make_double2(1.0, 0.0);
+        }
       }
     }
     if (!bar()) return false;
@@ -123,6 +135,12 @@ __global__ __launch_bounds__(64 * NW, (T == 4 && K == 4) ? 2 : 1) void nrgf_spli
       sacc_zero<TR, T, NW>(sa);
       for (int c = c0; c < i; ++c) smma<TR, T, NW>(sa, P(R + (size_t)c * bpbp), P(Ublk(c, i)), -1.0, row0);
       sstore<TR, T, NW>(sa, R + (size_t)i * bpbp, BP, BP, BP, row0);
+      for (int tr = 1; tr < a.nr && tr < i; ++tr) {
+        sacc_zero<TR, T, NW>(sa);
+        for (int c = c0; c < i; ++c)
+          smma<TR, T, NW>(sa, c <= tr ? Pb(Gblk(tr, c)) : P(Rrow(tr, c)), P(Ublk(c, i)), -1.0, row0);
+        sstore<TR, T, NW>(sa, Rrow(tr, i), BP, BP, BP, row0);
+      }
       if (!bar()) return false;
       sload<TR, T, NW>(sa, P(g + (size_t)i * bpbp), row0);
       for (int c = c0; c < i; ++c) smma<TR, T, NW>(sa, P(Lblk(i, c)), Pb(Gblk(c, i)), -1.0, row0);
@@ -137,6 +155,17 @@ __global__ __launch_bounds__(64 * NW, (T == 4 && K == 4) ? 2 : 1) void nrgf_spli
     if (threadIdx.x == 0) atomicOr(info, RGF_INFO_SYNC_TIMEOUT);
     if (leader && threadIdx.x == 0 && a.T) a.T[e] = __builtin_nan("");
     return;
+  }
+  if (a.rows_last) {
+    // blocks (tr, l-1), each workgroup its own rows: from the band when tr = l-1,
+    // else from the propagated rows
+    for (int tr = 0; tr < a.nr && tr < l; ++tr) {
+      if (tr == l - 1)
+        sload<TR, T, NW>(sa, Pb(Gblk(tr, l - 1)), row0);
+      else
+        sload<TR, T, NW>(sa, P(tr == 0 ? R + (size_t)(l - 1) * bpbp : Rrow(tr, l - 1)), row0);
+      sstore<TR, T, NW>(sa, a.rows_last + ((size_t)e * a.nr + tr) * bb, b, b, b, row0);
+    }
   }
   if (!leader) return;
   Acc<T, NW> acc;

@@ -227,7 +227,7 @@ def test_native_ndiagonal_ddrgf_workspace(l, b, w, m, ne):
     red_chain = ((4 * wr + 3) * lr + 3 + (w - 1) * lr) * B
     band = (2 * wr + 1) * lr * b * b * 16 * ne
     want = (al(chain * ne * m) + 2 * al(band) + al(ne * w * b * b * 16) + al(red_chain * ne)
-            + al(ne * 4 * B) + al(ne * m * 4) + al(ne * 4) + al(4))
+            + al(ne * 4 * B) + al(ne * m * 4) + al(ne * 4) + al(4) + al(64 * ne))
     assert p.workspace_bytes == want
     p.close()
 
