@@ -393,6 +393,8 @@ def solve(H, sigma_L, sigma_R, energies, eta_d: float = 0.0, method: str = "rgf"
             rec = dispatch.choose(l, b, w, ne, dispatch.gpu_measure(H, sigma_L, sigma_R, energies, eta_d, precision),
                                   precision=precision, device=f"cuda{H.device.index or 0}")
             method, domains, inner = rec["method"], rec["domains"], rec.get("inner_domains", 0)
+            if method == "ddrgf_fused":
+                method, ddrgf_form = "ddrgf", "fused"
         else:
             inner = 0
         plan = Plan(l, b, w, ne, method=method, precision=precision, domains=domains,

@@ -34,8 +34,9 @@ def candidates(l: int, b: int, w: int, precision: str = "fp64",
                methods: Iterable[str] = ("rgf", "ddrgf")) -> List[Tuple]:
     """Admissible candidates: ("rgf", 0), the sequential sweep; ("ddrgf", m), DDRGF
     (FP64 only) with separators of w layers and interiors of at least w layers (native
-    n-diagonal interiors for w > 1); ("ddrgf", m, m2), two-level DDRGF with m2 inner
-    pairs, for w = 1, m >= 16 and m2 in {2, 4, 8} with m >= 2 m2."""
+    n-diagonal interiors for w > 1); ("ddrgf_fused", m), for w > 1 the same on w-layer
+    super-blocks (l divisible by w, w b <= 128); ("ddrgf", m, m2), two-level DDRGF with
+    m2 inner pairs, for w = 1, m >= 16 and m2 in {2, 4, 8} with m >= 2 m2."""
     out: List[Tuple] = []
     if "rgf" in methods:
         out.append(("rgf", 0))
@@ -44,6 +45,8 @@ def candidates(l: int, b: int, w: int, precision: str = "fp64",
             if l - m * w < m * w:
                 continue
             out.append(("ddrgf", m))
+            if w > 1 and l % w == 0 and w * b <= 128 and l // w - m >= m:
+                out.append(("ddrgf_fused", m))
             if m >= 16 and w == 1:
                 out += [("ddrgf", m, m2) for m2 in (2, 4, 8) if m >= 2 * m2]
     return out
@@ -120,7 +123,9 @@ def gpu_measure(H, sigma_L, sigma_R, energies, eta_d: float = 0.0, precision: st
     ne = energies.shape[0]
 
     def measure(method: str, m: int, m2: int = 0) -> float:
-        plan = binding.Plan(l, b, w, ne, method=method, precision=precision, domains=m, inner_domains=m2)
+        form = "fused" if method == "ddrgf_fused" else "native"
+        plan = binding.Plan(l, b, w, ne, method="ddrgf" if method == "ddrgf_fused" else method,
+                            precision=precision, domains=m, inner_domains=m2, ddrgf_form=form)
         ws = torch.empty((plan.workspace_bytes,), dtype=torch.uint8, device=H.device)
         G = torch.empty((ne, nb, l, b, b), dtype=torch.complex128, device=H.device)
         T = torch.empty((ne,), dtype=torch.float64, device=H.device)

@@ -13,7 +13,11 @@ def test_candidates():
     # w = 2: native n-diagonal DDRGF, interiors of at least w layers, one level only
     assert [x for x in dispatch.candidates(512, 64, 2, "fp64") if x[0] == "ddrgf"] == \
         [("ddrgf", m) for m in (2, 4, 8, 16, 32)]
+    assert [x for x in dispatch.candidates(512, 64, 2, "fp64") if x[0] == "ddrgf_fused"] == \
+        [("ddrgf_fused", m) for m in (2, 4, 8, 16, 32)]
     assert [x[1] for x in dispatch.candidates(511, 100, 2, "fp64") if x[0] == "ddrgf"] == [2, 4, 8, 16, 32]
+    assert not [x for x in dispatch.candidates(511, 100, 2, "fp64") if x[0] == "ddrgf_fused"]
+    assert not [x for x in dispatch.candidates(512, 100, 2, "fp64") if x[0] == "ddrgf_fused"]
     assert [x[1] for x in dispatch.candidates(30, 64, 3, "fp64") if x[0] == "ddrgf"] == [2, 4]
     assert [x[1] for x in dispatch.candidates(10, 8, 1, "fp64") if x[0] == "ddrgf"] == [2, 4]
     # mixed precision: sequential only; methods filter

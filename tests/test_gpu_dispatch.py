@@ -60,3 +60,26 @@ def test_auto_config2_choice(lib, table):
     assert t[key] == min(t.values())
     torch.cuda.synchronize()
     free_gpu()
+
+
+def test_auto_pentadiagonal(lib, table):
+    """w = 2: the sequential sweep, native DDRGF and the super-block form are all timed;
+    the choice is the fastest and its results pass that method's rule."""
+    import torch
+    wl = make_random(40, 16, 2, 4, seed=5252, eta=1e-3)
+    H, sL, sR, E = to_dev(wl)
+    G, T, info = lib.solve(H, sL, sR, E, eta_d=0.0, method="auto")
+    torch.cuda.synchronize()
+    rec = list(table._cache.values())[0]
+    print(f"auto choice for 40 x 16, w = 2, 4 energies: {rec}", flush=True)
+    t = rec["timings_ms"]
+    assert "rgf/0" in t and "ddrgf/4" in t and "ddrgf_fused/4" in t
+    key = f"{rec['method']}/{rec['domains']}"
+    assert t[key] == min(t.values())
+    assert bool((info == 0).all())
+    Gn, Tn = G.cpu().numpy(), T.cpu().numpy()
+    if rec["method"] == "rgf":
+        check_fp64("auto w=2", Gn, Tn, range(4), oracle_results("nrgf", wl, range(4)), 2, 16)
+    else:
+        check_dd("auto w=2", Gn, Tn, range(4), oracle_results("ddrgf", wl, range(4), m=rec["domains"]),
+                 oracle_results("dense", wl, range(4)), 2)
